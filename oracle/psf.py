@@ -1,0 +1,58 @@
+"""PSF formation from the pupil phase (Sec. 2.2, Eq. 2):
+
+    h = | F{ W(rho) exp(-j phi(rho)) } |^2,   phi = sum_j alpha_j Z_j.
+
+Sampling reading (the paper leaves it to its supplement): the pupil of
+diameter D is sampled on Np x Np cell-centred points, zero-padded to
+Nfft = Q*Np (Q = 2 is Nyquist sampling of the diffraction-limited PSF), the
+power spectrum is centred with fftshift, cropped to P x P around DC and
+normalised to unit sum.  Tilts (Noll 2, 3) are left out, which centres the
+PSF (Sec. 3.2).
+
+Parity: pinned (Parseval and the zero-phase peak exactly; zero phase against
+the Airy pattern with the error shrinking as Np grows).
+"""
+import numpy as np
+
+from .zernike import zernike
+
+
+def pupil_grid(Np: int):
+    """(rho, theta, mask) on Np x Np cell-centred samples of the unit disk;
+    rows are y, columns are x."""
+    c = (2.0 * np.arange(Np) + 1.0 - Np) / Np
+    y, x = np.meshgrid(c, c, indexing="ij")
+    rho = np.hypot(x, y)
+    theta = np.arctan2(y, x)
+    return rho, theta, (rho <= 1.0).astype(np.float64)
+
+
+def zernike_stack(modes, Np: int) -> np.ndarray:
+    """Z_j sampled on the pupil grid for each Noll index in ``modes``."""
+    rho, theta, _ = pupil_grid(Np)
+    return np.stack([zernike(j, rho, theta) for j in modes])
+
+
+def psf_from_phase(phase: np.ndarray, mask: np.ndarray, Q: int, P: int, normalise: bool = True) -> np.ndarray:
+    """Eq. 2 for one or more pupil phases [..., Np, Np] -> PSFs [..., P, P]."""
+    Np = mask.shape[-1]
+    nfft = Q * Np
+    field = mask * np.exp(-1j * phase)
+    pad = np.zeros(phase.shape[:-2] + (nfft, nfft), dtype=np.complex128)
+    pad[..., :Np, :Np] = field
+    h = np.abs(np.fft.fft2(pad)) ** 2
+    h = np.fft.fftshift(h, axes=(-2, -1))
+    R = (P - 1) // 2
+    c = nfft // 2
+    h = h[..., c - R:c + R + 1, c - R:c + R + 1]
+    if normalise:
+        h = h / h.sum(axis=(-2, -1), keepdims=True)
+    return h
+
+
+def psf_from_zernike(alpha: np.ndarray, modes, Np: int = 32, Q: int = 2, P: int = 33) -> np.ndarray:
+    """PSFs for Zernike coefficient vectors alpha [..., len(modes)]."""
+    Z = zernike_stack(modes, Np)
+    _, _, mask = pupil_grid(Np)
+    phase = np.tensordot(np.asarray(alpha, dtype=np.float64), Z, axes=([-1], [0]))
+    return psf_from_phase(phase, mask, Q, P)
