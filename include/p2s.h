@@ -1,0 +1,186 @@
+/*
+ * p2s.h -- C ABI of the MI355X (gfx950) hot path of the phase-to-space (P2S)
+ * turbulence simulator (Mao, Chimitt & Chan, ICCV 2021).
+ *
+ * One frame goes through four stages, each a call below and all four chained
+ * by p2s_simulate:
+ *   fields  -- per-pixel Zernike coefficient planes alpha_j(x), spatially
+ *              correlated (Sec. 2.2 Eq. 1 and Sec. 3.4), here made by
+ *              filtering seeded white noise with a Gaussian PSD;
+ *   mlp     -- the P2S network mapping alpha_4.. to the basis weights
+ *              beta_m(x) at every pixel (Sec. 3.3);
+ *   blur    -- the spatially varying blur written as M invariant
+ *              convolutions with the basis PSFs and a per-pixel weighted sum
+ *              (Sec. 3.1, Eq. 4-5), fused so that the convolution outputs
+ *              never leave the chip;
+ *   warp    -- the tilt displacement by alpha_2, alpha_3 after the blur
+ *              (Sec. 2.2 and 3.3).
+ *
+ * Conventions shared by every call
+ *   - Pointers marked "device" are device memory of the current HIP device;
+ *     "host" pointers are host memory.  The caller owns every data buffer and
+ *     the workspace; the library owns only the handles it creates and never
+ *     frees caller memory.
+ *   - Images are planar float32, [C][H][W], row-major, no padding.
+ *   - Field planes are float32 [n_zernike][H][W]: plane p holds Noll mode
+ *     j = p + 2 (plane 0 = x-tilt alpha_2, plane 1 = y-tilt alpha_3, planes
+ *     2.. = alpha_4..), in radians of pupil phase.
+ *   - Basis weights w are float32 [H*W][K] (pixel-major, K contiguous).
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Every compute call
+ *     only enqueues work on it and returns; results are ready once the stream
+ *     is synchronised.
+ *   - Return value: P2S_OK (0) or a negative p2s_status.  Arguments are
+ *     validated on the host before anything is enqueued; on a validation
+ *     error nothing is written.  p2s_last_error() gives a message for the
+ *     last failure on the calling thread.  No C++ exception crosses the ABI.
+ */
+#ifndef P2S_H
+#define P2S_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define P2S_ABI_VERSION 1
+
+typedef enum {
+    P2S_OK = 0,
+    P2S_EINVAL = -1,        /* bad argument, size or relationship          */
+    P2S_ENOMEM = -2,        /* device or host allocation failed            */
+    P2S_EDEVICE = -3,       /* a HIP call or kernel launch failed           */
+    P2S_EUNSUPPORTED = -4   /* valid request this build does not implement */
+} p2s_status;
+
+typedef enum {
+    P2S_FP32 = 0,     /* FP32 MFMA for network and blur                     */
+    P2S_BF16 = 1,     /* BF16 MFMA, FP32 accumulation; network activations
+                         enter as a bf16 hi + lo pair, weights w stay FP32   */
+    P2S_FP8E4M3 = 2   /* reserved: FP8 E4M3 blur                            */
+} p2s_precision;
+
+/* Opaque, immutable, device-resident handles; safe to share across streams. */
+typedef struct p2s_basis_s* p2s_basis_t;
+typedef struct p2s_mlp_s* p2s_mlp_t;
+
+/* Optional parameters; pass NULL for the defaults shown. */
+typedef struct {
+    float corr_len_px;   /* 16: Gaussian standard deviation, in pixels, of the
+                            covariance of every field plane                  */
+    float q_sampling;    /* 2: image samples per lambda/D; a tilt alpha moves
+                            the image by 2*q*alpha/pi pixels                   */
+} p2s_params;
+
+/* Limits of this build. */
+#define P2S_MAX_K 128          /* basis functions                            */
+#define P2S_MAX_P 33           /* PSF side (odd)                             */
+#define P2S_MAX_ZERNIKE 64     /* field planes (Noll 2 .. 65)                */
+#define P2S_MAX_WIDTH 128      /* widest network layer                       */
+#define P2S_MAX_LAYERS 4
+#define P2S_MAX_SIDE 16384     /* H, W                                       */
+#define P2S_MAX_CHANNELS 4
+
+int p2s_version(void);
+const char* p2s_last_error(void);
+
+/* ---------------------------------------------------------------- host -- */
+
+/* Variance of Noll mode j >= 2 of Kolmogorov turbulence per (D/r0)^(5/3):
+ * the diagonal of R_Z (Sec. 2.2).  Computed as
+ * K (n+1) Gamma(n-5/6) / (Gamma(17/6)^2 Gamma(n+23/6)) for radial order n,
+ * K fixed so that the variances of all modes j >= 2 sum to 1.0299, Noll's
+ * piston-removed phase variance.  Writes *out; EINVAL for j < 2. */
+int p2s_noll_variance(int j, double* out);
+
+/* Side of the periodic noise grid used for an image side n: the smallest
+ * 2^a 3^b 5^c >= n + ceil(4 * corr_len_px).  Writes *nf. */
+int p2s_field_grid(int n, float corr_len_px, int* nf);
+
+/* Device bytes p2s_make_fields needs as workspace for an H x W frame. */
+size_t p2s_fields_workspace_bytes(int H, int W, int n_zernike, const p2s_params* params);
+
+/* Device bytes p2s_simulate needs as workspace: fields, weights, blurred
+ * image and the field generator's intermediate (256-byte aligned pieces). */
+size_t p2s_workspace_bytes(int C, int H, int W, int n_zernike, int K, const p2s_params* params);
+
+/* ------------------------------------------------------------- handles -- */
+
+/* Upload a PSF basis phi_m (Sec. 3.1 Eq. 4, learned by PCA in Sec. 3.2).
+ * host_basis: host, float64 [K][P][P]; tap [i][j] sits at offset
+ * (i - R, j - R), R = (P-1)/2, and acts as a convolution kernel.
+ * K in [1, P2S_MAX_K], P odd in [1, P2S_MAX_P].  The library keeps FP32 and
+ * BF16 copies laid out for its MFMA kernels.  *out receives the handle. */
+int p2s_basis_create(const double* host_basis, int K, int P, p2s_basis_t* out);
+int p2s_basis_destroy(p2s_basis_t basis);
+int p2s_basis_info(p2s_basis_t basis, int* K, int* P);
+
+/* Upload the P2S network (Sec. 3.3): n_layers fully connected layers
+ * y = W x + b with ReLU after all but the last.  dims[n_layers+1] are the
+ * layer widths (dims[0] = number of high-order modes, dims[n_layers] = K);
+ * each width in [1, P2S_MAX_WIDTH], n_layers in [1, P2S_MAX_LAYERS].
+ * host_W[l]: host float32 [dims[l+1]][dims[l]]; host_b[l]: host float32
+ * [dims[l+1]] (a NULL host_b or host_b[l] means zero bias).  The BF16 path
+ * rounds the weights to bfloat16 (exact if they are bf16-representable). */
+int p2s_mlp_create(int n_layers, const int* dims, const float* const* host_W,
+                   const float* const* host_b, p2s_mlp_t* out);
+int p2s_mlp_destroy(p2s_mlp_t mlp);
+int p2s_mlp_info(p2s_mlp_t mlp, int* n_in, int* n_out);
+
+/* ------------------------------------------------------------- compute -- */
+
+/* Stage 1: correlated Zernike fields.  For each plane p (Noll j = p + 2):
+ * white noise n_p on the periodic Nf_y x Nf_x grid (p2s_field_grid), drawn
+ * from Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter
+ * (c >> 2, r, p, 0) for cell (r, c), Box-Muller as the oracle documents;
+ * filtered by sqrt(S), S(f) = exp(-2 pi^2 l^2 |f|^2) normalised to mean 1;
+ * cropped to the top-left H x W and scaled by sqrt(V_j (D/r0)^(5/3)).
+ * fields: device float32 [n_zernike][H][W].  ws: device, at least
+ * p2s_fields_workspace_bytes.  n_zernike in [1, P2S_MAX_ZERNIKE]. */
+int p2s_make_fields(int H, int W, double D_over_r0, int n_zernike, uint64_t seed,
+                    const p2s_params* params, float* fields, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* Stage 2: the P2S network at every pixel (Sec. 3.3).  Reads planes
+ * 2 .. n_zernike-1 of `fields` (device [n_zernike][H][W]); requires
+ * n_zernike - 2 == the network's input width.  Writes w: device float32
+ * [H*W][K], K = the network's output width.  precision: P2S_FP32 or
+ * P2S_BF16. */
+int p2s_mlp(p2s_mlp_t mlp, const float* fields, int n_zernike, int H, int W,
+            p2s_precision precision, float* w, void* stream);
+
+/* Stage 3: fused basis blur (Sec. 3.1, Eq. 5):
+ *   out_c(x) = sum_k w_k(x) sum_u phi_k(u) image_c(clamp(x - u)),
+ * replicate border, the same weights for every channel (Sec. 3.5).
+ * image, out: device float32 [C][H][W] (must not overlap); w: device float32
+ * [H*W][K] with K = the basis size.  precision: P2S_FP32 (any odd P) or
+ * P2S_BF16 (P = 8a + 1, e.g. 17 or 33). */
+int p2s_blur(const float* image, int C, int H, int W, p2s_basis_t basis, const float* w,
+             p2s_precision precision, float* out, void* stream);
+
+/* Stage 4: tilt warp (Sec. 2.2, 3.3): out_c(y, x) = bilinear sample of in_c
+ * at (y + s*tilt[1](y,x), x + s*tilt[0](y,x)), s = 2 q / pi, sample position
+ * clamped to the image.  in, out: device float32 [C][H][W] (must not
+ * overlap); tilt: device float32 [2][H][W] (planes 0 and 1 of the fields). */
+int p2s_warp(const float* in, int C, int H, int W, const float* tilt,
+             const p2s_params* params, float* out, void* stream);
+
+/* One frame end to end: fields -> mlp -> blur -> warp, intermediates in ws
+ * (device, at least p2s_workspace_bytes).  image, out: device float32
+ * [C][H][W].  n_zernike - 2 must equal the network's input width and the
+ * network's output width must equal the basis size K. */
+int p2s_simulate(const float* image, int C, int H, int W, double D_over_r0, int n_zernike,
+                 p2s_basis_t basis, p2s_mlp_t mlp, uint64_t seed, p2s_precision precision,
+                 const p2s_params* params, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Test hook: the generator behind p2s_make_fields for one plane.  raw:
+ * device uint32 [Nfy][ceil(Nfx/4)][4], the four Philox outputs per counter;
+ * normals: device float32 [Nfy][Nfx] (may be NULL). */
+int p2s_debug_noise(int Nfy, int Nfx, int plane, uint64_t seed, uint32_t* raw, float* normals,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* P2S_H */

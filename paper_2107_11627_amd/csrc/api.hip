@@ -1,0 +1,589 @@
+// Host side of libp2s: argument validation, handle creation (basis and
+// network packed into MFMA operand layouts), workspace carving and the chain
+// of launches behind each public call.  See include/p2s.h for the contract.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+struct p2s_basis_s {
+    p2s::Basis b;
+};
+struct p2s_mlp_s {
+    p2s::Mlp m;
+};
+
+namespace p2s {
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() {
+    g_err.clear();
+    return P2S_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(P2S_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// -------------------------------------------------------------- Noll R_Z
+// (n+1) Gamma(n - 5/6) / (Gamma(17/6)^2 Gamma(n + 23/6)) for radial order n.
+double noll_shape(int n) {
+    return (n + 1) * std::exp(std::lgamma(n - 5.0 / 6.0) - 2.0 * std::lgamma(17.0 / 6.0) - std::lgamma(n + 23.0 / 6.0));
+}
+
+// Constant fixing sum_{j>=2} V_j to Noll's piston-removed variance 1.0299.
+double noll_constant() {
+    static const double kc = [] {
+        double s = 0.0;
+        for (int n = 199999; n >= 1; --n) s += (n + 1) * noll_shape(n);   // small terms first
+        return 1.0299 / s;
+    }();
+    return kc;
+}
+
+int radial_order(int j) {
+    int n = 0;
+    while ((n + 1) * (n + 2) / 2 < j) ++n;
+    return n;
+}
+
+double noll_var(int j) { return noll_constant() * noll_shape(radial_order(j)); }
+
+// ---------------------------------------------------------------- fields
+bool smooth5(int n) {
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+int grid_of(int n, float corr_len) {
+    long v = (long)n + (long)std::ceil(4.0 * (double)corr_len);
+    while (!smooth5((int)v)) ++v;
+    return (int)v;
+}
+
+struct Params {
+    float corr_len = 16.0f;
+    float q = 2.0f;
+};
+
+int read_params(const p2s_params* p, Params* out) {
+    Params r;
+    if (p) {
+        r.corr_len = p->corr_len_px;
+        r.q = p->q_sampling;
+    }
+    if (!(std::isfinite(r.corr_len) && r.corr_len > 0.0f && r.corr_len <= 1024.0f))
+        return fail(P2S_EINVAL, "corr_len_px must be in (0, 1024], got %g", (double)r.corr_len);
+    if (!(std::isfinite(r.q) && r.q > 0.0f && r.q <= 64.0f))
+        return fail(P2S_EINVAL, "q_sampling must be in (0, 64], got %g", (double)r.q);
+    *out = r;
+    return P2S_OK;
+}
+
+// Largest FFT length the LDS of one workgroup holds (one transform, ping-pong
+// buffers, twiddles and filter): 16 (N|1) + 12 N bytes <= 160 KiB.
+constexpr int kMaxFftLen = 5800;
+
+size_t fields_ws(int H, int W, int nz, const Params& pr) {
+    const int Nfy = grid_of(H, pr.corr_len);
+    return align256((size_t)nz * Nfy * W * sizeof(float));
+}
+
+int check_frame(int C, int H, int W) {
+    if (C < 1 || C > P2S_MAX_CHANNELS) return fail(P2S_EINVAL, "C must be in [1, %d], got %d", P2S_MAX_CHANNELS, C);
+    if (H < 1 || W < 1 || H > P2S_MAX_SIDE || W > P2S_MAX_SIDE)
+        return fail(P2S_EINVAL, "H, W must be in [1, %d], got %d x %d", P2S_MAX_SIDE, H, W);
+    return P2S_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+int make_fields_impl(int H, int W, double d, int nz, uint64_t seed, const Params& pr, float* F, void* ws,
+                     size_t ws_bytes, hipStream_t s) {
+    if (H < 1 || W < 1 || H > P2S_MAX_SIDE || W > P2S_MAX_SIDE)
+        return fail(P2S_EINVAL, "H, W must be in [1, %d], got %d x %d", P2S_MAX_SIDE, H, W);
+    if (nz < 1 || nz > P2S_MAX_ZERNIKE) return fail(P2S_EINVAL, "n_zernike must be in [1, %d], got %d", P2S_MAX_ZERNIKE, nz);
+    if (!(std::isfinite(d) && d >= 0.0)) return fail(P2S_EINVAL, "D/r0 must be finite and >= 0, got %g", d);
+    if (!F) return fail(P2S_EINVAL, "fields is NULL");
+    if (!ws) return fail(P2S_EINVAL, "workspace is NULL");
+    FieldPlan fp{};
+    fp.H = H;
+    fp.W = W;
+    fp.Nfy = grid_of(H, pr.corr_len);
+    fp.Nfx = grid_of(W, pr.corr_len);
+    if (fp.Nfy > kMaxFftLen || fp.Nfx > kMaxFftLen)
+        return fail(P2S_EUNSUPPORTED, "noise grid %d x %d exceeds the single-workgroup FFT limit %d", fp.Nfy, fp.Nfx,
+                    kMaxFftLen);
+    const size_t need = fields_ws(H, W, nz, pr);
+    if (ws_bytes < need) return fail(P2S_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    fp.nrad_x = factor_radices(fp.Nfx, fp.rad_x);
+    fp.nrad_y = factor_radices(fp.Nfy, fp.rad_y);
+    if (!fp.nrad_x || !fp.nrad_y) return fail(P2S_EINVAL, "internal: grid not 5-smooth");
+    fp.nplanes = nz;
+    fp.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    fp.k1 = (uint32_t)(seed >> 32);
+    fp.corr_len = pr.corr_len;
+    const double a = 2.0 * M_PI * M_PI * (double)pr.corr_len * (double)pr.corr_len;
+    auto mean_s = [&](int N) {
+        double m = 0.0;
+        for (int k = 0; k < N; ++k) {
+            const int kk = (k < (N + 1) / 2) ? k : k - N;
+            const double f = (double)kk / N;
+            m += std::exp(-a * f * f);
+        }
+        return m / N;
+    };
+    fp.scale_x = (float)(1.0 / (std::sqrt(mean_s(fp.Nfx)) * fp.Nfx));
+    fp.scale_y = (float)(1.0 / (std::sqrt(mean_s(fp.Nfy)) * fp.Nfy));
+    const double d53 = std::pow(d, 5.0 / 3.0);
+    for (int p = 0; p < nz; ++p) fp.sigma[p] = (float)std::sqrt(noll_var(p + 2) * d53);
+    hipError_t e = launch_fields(fp, (float*)ws, F, s);
+    if (e != hipSuccess) return hip_fail(e, "field kernels");
+    return P2S_OK;
+}
+
+// ----------------------------------------------------------------- basis
+int pack_basis(const double* hb, int K, int P, Basis* B) {
+    const int R = (P - 1) / 2;
+    const int U = P * P;
+    B->K = K;
+    B->P = P;
+    B->R = R;
+    B->nmb = (K + 15) / 16;
+    B->t4 = (U + 3) / 4;
+    auto tap = [&](int k, int dy, int dx) -> double {   // correlation-order tap
+        if (k >= K || dy < -R || dy > R || dx < -R || dx > R) return 0.0;
+        return hb[((size_t)k * P + (R - dy)) * P + (R - dx)];
+    };
+    std::vector<float> f32((size_t)(B->t4 + 2) * B->nmb * 64, 0.0f);   // two zero steps: prefetch slack
+    for (int t = 0; t < B->t4; ++t)
+        for (int mb = 0; mb < B->nmb; ++mb)
+            for (int L = 0; L < 64; ++L) {
+                const int u = 4 * t + L / 16, k = 16 * mb + L % 16;
+                double v = 0.0;
+                if (u < U) v = tap(k, u / P - R, u % P - R);
+                f32[((size_t)t * B->nmb + mb) * 64 + L] = (float)v;
+            }
+    B->bf16_ok = (P % 8 == 1 && P >= 9);
+    std::vector<uint16_t> h16;
+    if (B->bf16_ok) {
+        const int A8 = P / 8, NROW = P * A8, NCOL = (P + 7) / 8;
+        B->t32 = (NROW + NCOL + 3) / 4;
+        h16.assign((size_t)(B->t32 + 2) * B->nmb * 64 * 8, 0);   // two zero steps: prefetch slack
+        for (int t = 0; t < B->t32; ++t)
+            for (int mb = 0; mb < B->nmb; ++mb)
+                for (int L = 0; L < 64; ++L)
+                    for (int e = 0; e < 8; ++e) {
+                        const int ch = 4 * t + L / 16, k = 16 * mb + L % 16;
+                        double v = 0.0;
+                        if (ch < NROW) v = tap(k, ch / A8 - R, (ch % A8) * 8 - R + e);
+                        else if (ch < NROW + NCOL) v = tap(k, -R + 8 * (ch - NROW) + e, R);
+                        h16[(((size_t)t * B->nmb + mb) * 64 + L) * 8 + e] = f32_to_bf16_rne((float)v);
+                    }
+    }
+    hipError_t e = hipMalloc(&B->f32, f32.size() * sizeof(float));
+    if (e != hipSuccess) return fail(P2S_ENOMEM, "hipMalloc basis: %s", hipGetErrorString(e));
+    e = hipMemcpy(B->f32, f32.data(), f32.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(B->f32);
+        return hip_fail(e, "upload basis");
+    }
+    B->bf16 = nullptr;
+    if (B->bf16_ok) {
+        e = hipMalloc(&B->bf16, h16.size() * sizeof(uint16_t));
+        if (e != hipSuccess) {
+            (void)hipFree(B->f32);
+            return fail(P2S_ENOMEM, "hipMalloc basis: %s", hipGetErrorString(e));
+        }
+        e = hipMemcpy(B->bf16, h16.data(), h16.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(B->f32);
+            (void)hipFree(B->bf16);
+            return hip_fail(e, "upload basis");
+        }
+    }
+    return P2S_OK;
+}
+
+// ------------------------------------------------------------------- mlp
+int pack_mlp(int L, const int* dims, const float* const* W, const float* const* b, Mlp* M) {
+    M->L = L;
+    for (int i = 0; i <= L; ++i) M->dims[i] = dims[i];
+    std::vector<float> w32, bias;
+    std::vector<uint16_t> w16;
+    for (int l = 0; l < L; ++l) {
+        const int in = dims[l], out = dims[l + 1];
+        const int nmo = (out + 15) / 16;
+        const float* Wl = W[l];
+        auto wat = [&](int r, int f) -> float { return (r < out && f < in) ? Wl[(size_t)r * in + f] : 0.0f; };
+        // FP32
+        const int nkc = (l == 0) ? (in + 3) / 4 : 4 * ((in + 15) / 16);
+        M->nkc32[l] = nkc;
+        M->off32[l] = w32.size() * sizeof(float);
+        for (int mb = 0; mb < nmo; ++mb)
+            for (int kc = 0; kc < nkc; ++kc)
+                for (int Ln = 0; Ln < 64; ++Ln) {
+                    const int g = Ln / 16, r = 16 * mb + Ln % 16;
+                    const int f = (l == 0) ? 4 * kc + g : 16 * (kc / 4) + 4 * g + kc % 4;
+                    w32.push_back(wat(r, f));
+                }
+        // BF16
+        const int nk16 = (l == 0) ? (in + 31) / 32 : ((in + 15) / 16 + 1) / 2;
+        M->nkc16[l] = nk16;
+        M->off16[l] = w16.size() * sizeof(uint16_t);
+        for (int mb = 0; mb < nmo; ++mb)
+            for (int kc = 0; kc < nk16; ++kc)
+                for (int Ln = 0; Ln < 64; ++Ln)
+                    for (int e = 0; e < 8; ++e) {
+                        const int g = Ln / 16, r = 16 * mb + Ln % 16;
+                        const int f = (l == 0) ? 32 * kc + 8 * g + e : 16 * (2 * kc + e / 4) + 4 * g + e % 4;
+                        w16.push_back(f32_to_bf16_rne(wat(r, f)));
+                    }
+        M->boff[l] = (int)bias.size();
+        for (int r = 0; r < 16 * nmo; ++r) bias.push_back((b && b[l] && r < out) ? b[l][r] : 0.0f);
+    }
+    M->bytes32 = w32.size() * sizeof(float);
+    M->bytes16 = w16.size() * sizeof(uint16_t);
+    M->w32 = nullptr;
+    M->w16 = nullptr;
+    M->bias = nullptr;
+    hipError_t e;
+    if ((e = hipMalloc(&M->w32, M->bytes32)) != hipSuccess || (e = hipMalloc(&M->w16, M->bytes16)) != hipSuccess ||
+        (e = hipMalloc(&M->bias, bias.size() * sizeof(float))) != hipSuccess) {
+        (void)hipFree(M->w32);
+        (void)hipFree(M->w16);
+        (void)hipFree(M->bias);
+        return fail(P2S_ENOMEM, "hipMalloc network: %s", hipGetErrorString(e));
+    }
+    if ((e = hipMemcpy(M->w32, w32.data(), M->bytes32, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(M->w16, w16.data(), M->bytes16, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(M->bias, bias.data(), bias.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(M->w32);
+        (void)hipFree(M->w16);
+        (void)hipFree(M->bias);
+        return hip_fail(e, "upload network");
+    }
+    return P2S_OK;
+}
+
+int check_prec(p2s_precision prec) {
+    if (prec == P2S_FP32 || prec == P2S_BF16) return P2S_OK;
+    if (prec == P2S_FP8E4M3) return fail(P2S_EUNSUPPORTED, "FP8 E4M3 precision is not available in this build");
+    return fail(P2S_EINVAL, "unknown precision %d", (int)prec);
+}
+
+int mlp_impl(const Mlp& m, const float* F, int nz, int H, int W, p2s_precision prec, float* w, hipStream_t s) {
+    if (H < 1 || W < 1 || H > P2S_MAX_SIDE || W > P2S_MAX_SIDE)
+        return fail(P2S_EINVAL, "H, W must be in [1, %d], got %d x %d", P2S_MAX_SIDE, H, W);
+    if (nz - 2 != m.dims[0])
+        return fail(P2S_EINVAL, "n_zernike - 2 = %d does not match the network input width %d", nz - 2, m.dims[0]);
+    if (!F || !w) return fail(P2S_EINVAL, "fields or w is NULL");
+    int rc = check_prec(prec);
+    if (rc) return rc;
+    const size_t HW = (size_t)H * W;
+    if (overlap(F, (size_t)nz * HW * 4, w, HW * m.dims[m.L] * 4)) return fail(P2S_EINVAL, "fields and w overlap");
+    // the kernel reads planes 2.. : pass a pointer to plane 2
+    hipError_t e = launch_mlp(m, F + 2 * HW, H, W, prec, w, s);
+    if (e != hipSuccess) return hip_fail(e, "network kernel");
+    return P2S_OK;
+}
+
+int blur_impl(const float* img, int C, int H, int W, const Basis& b, const float* w, p2s_precision prec, float* out,
+              hipStream_t s) {
+    int rc = check_frame(C, H, W);
+    if (rc) return rc;
+    rc = check_prec(prec);
+    if (rc) return rc;
+    if (!img || !w || !out) return fail(P2S_EINVAL, "image, w or out is NULL");
+    const size_t n = (size_t)C * H * W * 4;
+    if (overlap(img, n, out, n)) return fail(P2S_EINVAL, "image and out overlap");
+    if (overlap(w, (size_t)H * W * b.K * 4, out, n)) return fail(P2S_EINVAL, "w and out overlap");
+    if (prec == P2S_BF16 && !b.bf16_ok)
+        return fail(P2S_EUNSUPPORTED, "BF16 blur needs a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", b.P);
+    hipError_t e = launch_blur(b, img, C, H, W, w, prec, out, s);
+    if (e != hipSuccess) return hip_fail(e, "blur kernel");
+    return P2S_OK;
+}
+
+int warp_impl(const float* in, int C, int H, int W, const float* tilt, const Params& pr, float* out, hipStream_t s) {
+    int rc = check_frame(C, H, W);
+    if (rc) return rc;
+    if (!in || !tilt || !out) return fail(P2S_EINVAL, "in, tilt or out is NULL");
+    const size_t n = (size_t)C * H * W * 4;
+    if (overlap(in, n, out, n)) return fail(P2S_EINVAL, "in and out overlap");
+    if (overlap(tilt, (size_t)2 * H * W * 4, out, n)) return fail(P2S_EINVAL, "tilt and out overlap");
+    const float scale = (float)(2.0 * (double)pr.q / M_PI);
+    hipError_t e = launch_warp(in, C, H, W, tilt, scale, out, s);
+    if (e != hipSuccess) return hip_fail(e, "warp kernel");
+    return P2S_OK;
+}
+
+struct SimLayout {
+    size_t fields, region2, blurred, total;
+};
+
+SimLayout sim_layout(int C, int H, int W, int nz, int K, const Params& pr) {
+    SimLayout L;
+    const size_t HW = (size_t)H * W;
+    L.fields = 0;
+    const size_t fb = align256((size_t)nz * HW * 4);
+    const size_t r2 = std::max(fields_ws(H, W, nz, pr), align256(HW * K * 4));
+    L.region2 = fb;
+    L.blurred = fb + r2;
+    L.total = L.blurred + align256((size_t)C * HW * 4);
+    return L;
+}
+
+}  // namespace
+
+uint16_t f32_to_bf16_rne(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+}  // namespace p2s
+
+using namespace p2s;
+
+extern "C" {
+
+int p2s_version(void) { return P2S_ABI_VERSION; }
+
+const char* p2s_last_error(void) { return g_err.c_str(); }
+
+int p2s_noll_variance(int j, double* out) {
+    if (j < 2) return fail(P2S_EINVAL, "Noll index must be >= 2, got %d", j);
+    if (!out) return fail(P2S_EINVAL, "out is NULL");
+    *out = noll_var(j);
+    return ok();
+}
+
+int p2s_field_grid(int n, float corr_len_px, int* nf) {
+    if (n < 1 || n > P2S_MAX_SIDE) return fail(P2S_EINVAL, "n must be in [1, %d], got %d", P2S_MAX_SIDE, n);
+    if (!(std::isfinite(corr_len_px) && corr_len_px > 0.0f && corr_len_px <= 1024.0f))
+        return fail(P2S_EINVAL, "corr_len_px must be in (0, 1024]");
+    if (!nf) return fail(P2S_EINVAL, "nf is NULL");
+    *nf = grid_of(n, corr_len_px);
+    return ok();
+}
+
+size_t p2s_fields_workspace_bytes(int H, int W, int n_zernike, const p2s_params* params) {
+    Params pr;
+    if (read_params(params, &pr) || H < 1 || W < 1 || H > P2S_MAX_SIDE || W > P2S_MAX_SIDE || n_zernike < 1 ||
+        n_zernike > P2S_MAX_ZERNIKE)
+        return 0;
+    return fields_ws(H, W, n_zernike, pr);
+}
+
+size_t p2s_workspace_bytes(int C, int H, int W, int n_zernike, int K, const p2s_params* params) {
+    Params pr;
+    if (read_params(params, &pr) || check_frame(C, H, W) || n_zernike < 1 || n_zernike > P2S_MAX_ZERNIKE || K < 1 ||
+        K > P2S_MAX_K)
+        return 0;
+    return sim_layout(C, H, W, n_zernike, K, pr).total;
+}
+
+int p2s_basis_create(const double* host_basis, int K, int P, p2s_basis_t* out) {
+    try {
+        if (!host_basis || !out) return fail(P2S_EINVAL, "host_basis or out is NULL");
+        if (K < 1 || K > P2S_MAX_K) return fail(P2S_EINVAL, "K must be in [1, %d], got %d", P2S_MAX_K, K);
+        if (P < 1 || P > P2S_MAX_P || P % 2 == 0) return fail(P2S_EINVAL, "P must be odd in [1, %d], got %d", P2S_MAX_P, P);
+        for (size_t i = 0; i < (size_t)K * P * P; ++i)
+            if (!std::isfinite(host_basis[i])) return fail(P2S_EINVAL, "basis value %zu is not finite", i);
+        auto* h = new (std::nothrow) p2s_basis_s();
+        if (!h) return fail(P2S_ENOMEM, "host allocation failed");
+        int rc = pack_basis(host_basis, K, P, &h->b);
+        if (rc) {
+            delete h;
+            return rc;
+        }
+        *out = h;
+        return ok();
+    } catch (...) {
+        return fail(P2S_ENOMEM, "host allocation failed");
+    }
+}
+
+int p2s_basis_destroy(p2s_basis_t basis) {
+    if (!basis) return ok();
+    (void)hipFree(basis->b.f32);
+    if (basis->b.bf16) (void)hipFree(basis->b.bf16);
+    delete basis;
+    return ok();
+}
+
+int p2s_basis_info(p2s_basis_t basis, int* K, int* P) {
+    if (!basis) return fail(P2S_EINVAL, "basis is NULL");
+    if (K) *K = basis->b.K;
+    if (P) *P = basis->b.P;
+    return ok();
+}
+
+int p2s_mlp_create(int n_layers, const int* dims, const float* const* host_W, const float* const* host_b,
+                   p2s_mlp_t* out) {
+    try {
+        if (!dims || !host_W || !out) return fail(P2S_EINVAL, "dims, host_W or out is NULL");
+        if (n_layers < 1 || n_layers > P2S_MAX_LAYERS)
+            return fail(P2S_EINVAL, "n_layers must be in [1, %d], got %d", P2S_MAX_LAYERS, n_layers);
+        for (int i = 0; i <= n_layers; ++i)
+            if (dims[i] < 1 || dims[i] > P2S_MAX_WIDTH)
+                return fail(P2S_EINVAL, "layer width %d must be in [1, %d], got %d", i, P2S_MAX_WIDTH, dims[i]);
+        if (dims[0] > P2S_MAX_ZERNIKE - 2)
+            return fail(P2S_EINVAL, "input width must be <= %d, got %d", P2S_MAX_ZERNIKE - 2, dims[0]);
+        if (dims[n_layers] > P2S_MAX_K) return fail(P2S_EINVAL, "output width must be <= %d", P2S_MAX_K);
+        for (int l = 0; l < n_layers; ++l) {
+            if (!host_W[l]) return fail(P2S_EINVAL, "host_W[%d] is NULL", l);
+            for (size_t i = 0; i < (size_t)dims[l] * dims[l + 1]; ++i)
+                if (!std::isfinite(host_W[l][i])) return fail(P2S_EINVAL, "weight %zu of layer %d is not finite", i, l);
+            if (host_b && host_b[l])
+                for (int i = 0; i < dims[l + 1]; ++i)
+                    if (!std::isfinite(host_b[l][i])) return fail(P2S_EINVAL, "bias %d of layer %d is not finite", i, l);
+        }
+        auto* h = new (std::nothrow) p2s_mlp_s();
+        if (!h) return fail(P2S_ENOMEM, "host allocation failed");
+        int rc = pack_mlp(n_layers, dims, host_W, host_b, &h->m);
+        if (rc) {
+            delete h;
+            return rc;
+        }
+        *out = h;
+        return ok();
+    } catch (...) {
+        return fail(P2S_ENOMEM, "host allocation failed");
+    }
+}
+
+int p2s_mlp_destroy(p2s_mlp_t mlp) {
+    if (!mlp) return ok();
+    (void)hipFree(mlp->m.w32);
+    (void)hipFree(mlp->m.w16);
+    (void)hipFree(mlp->m.bias);
+    delete mlp;
+    return ok();
+}
+
+int p2s_mlp_info(p2s_mlp_t mlp, int* n_in, int* n_out) {
+    if (!mlp) return fail(P2S_EINVAL, "mlp is NULL");
+    if (n_in) *n_in = mlp->m.dims[0];
+    if (n_out) *n_out = mlp->m.dims[mlp->m.L];
+    return ok();
+}
+
+int p2s_make_fields(int H, int W, double D_over_r0, int n_zernike, uint64_t seed, const p2s_params* params,
+                    float* fields, void* ws, size_t ws_bytes, void* stream) {
+    Params pr;
+    int rc = read_params(params, &pr);
+    if (rc) return rc;
+    rc = make_fields_impl(H, W, D_over_r0, n_zernike, seed, pr, fields, ws, ws_bytes, (hipStream_t)stream);
+    return rc ? rc : ok();
+}
+
+int p2s_mlp(p2s_mlp_t mlp, const float* fields, int n_zernike, int H, int W, p2s_precision precision, float* w,
+            void* stream) {
+    if (!mlp) return fail(P2S_EINVAL, "mlp is NULL");
+    int rc = mlp_impl(mlp->m, fields, n_zernike, H, W, precision, w, (hipStream_t)stream);
+    return rc ? rc : ok();
+}
+
+int p2s_blur(const float* image, int C, int H, int W, p2s_basis_t basis, const float* w, p2s_precision precision,
+             float* out, void* stream) {
+    if (!basis) return fail(P2S_EINVAL, "basis is NULL");
+    int rc = blur_impl(image, C, H, W, basis->b, w, precision, out, (hipStream_t)stream);
+    return rc ? rc : ok();
+}
+
+int p2s_warp(const float* in, int C, int H, int W, const float* tilt, const p2s_params* params, float* out,
+             void* stream) {
+    Params pr;
+    int rc = read_params(params, &pr);
+    if (rc) return rc;
+    rc = warp_impl(in, C, H, W, tilt, pr, out, (hipStream_t)stream);
+    return rc ? rc : ok();
+}
+
+int p2s_simulate(const float* image, int C, int H, int W, double D_over_r0, int n_zernike, p2s_basis_t basis,
+                 p2s_mlp_t mlp, uint64_t seed, p2s_precision precision, const p2s_params* params, float* out,
+                 void* ws, size_t ws_bytes, void* stream) {
+    Params pr;
+    int rc = read_params(params, &pr);
+    if (rc) return rc;
+    if (!basis || !mlp) return fail(P2S_EINVAL, "basis or mlp is NULL");
+    rc = check_frame(C, H, W);
+    if (rc) return rc;
+    rc = check_prec(precision);
+    if (rc) return rc;
+    if (n_zernike < 3 || n_zernike > P2S_MAX_ZERNIKE)
+        return fail(P2S_EINVAL, "n_zernike must be in [3, %d], got %d", P2S_MAX_ZERNIKE, n_zernike);
+    if (mlp->m.dims[0] != n_zernike - 2)
+        return fail(P2S_EINVAL, "n_zernike - 2 = %d does not match the network input width %d", n_zernike - 2,
+                    mlp->m.dims[0]);
+    if (mlp->m.dims[mlp->m.L] != basis->b.K)
+        return fail(P2S_EINVAL, "network output width %d does not match the basis size K = %d",
+                    mlp->m.dims[mlp->m.L], basis->b.K);
+    if (precision == P2S_BF16 && !basis->b.bf16_ok)
+        return fail(P2S_EUNSUPPORTED, "BF16 blur needs a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", basis->b.P);
+    if (!image || !out || !ws) return fail(P2S_EINVAL, "image, out or workspace is NULL");
+    if (!(std::isfinite(D_over_r0) && D_over_r0 >= 0.0)) return fail(P2S_EINVAL, "D/r0 must be finite and >= 0");
+    const int Nfy = grid_of(H, pr.corr_len), Nfx = grid_of(W, pr.corr_len);
+    if (Nfy > kMaxFftLen || Nfx > kMaxFftLen)
+        return fail(P2S_EUNSUPPORTED, "noise grid %d x %d exceeds the single-workgroup FFT limit %d", Nfy, Nfx, kMaxFftLen);
+    const SimLayout L = sim_layout(C, H, W, n_zernike, basis->b.K, pr);
+    if (ws_bytes < L.total) return fail(P2S_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    const size_t n = (size_t)C * H * W * 4;
+    if (overlap(image, n, out, n)) return fail(P2S_EINVAL, "image and out overlap");
+    if (overlap(ws, L.total, out, n) || overlap(ws, L.total, image, n))
+        return fail(P2S_EINVAL, "workspace overlaps image or out");
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)ws;
+    float* F = (float*)(base + L.fields);
+    float* r2 = (float*)(base + L.region2);
+    float* bl = (float*)(base + L.blurred);
+    rc = make_fields_impl(H, W, D_over_r0, n_zernike, seed, pr, F, r2, L.blurred - L.region2, s);
+    if (rc) return rc;
+    rc = mlp_impl(mlp->m, F, n_zernike, H, W, precision, r2, s);
+    if (rc) return rc;
+    rc = blur_impl(image, C, H, W, basis->b, r2, precision, bl, s);
+    if (rc) return rc;
+    rc = warp_impl(bl, C, H, W, F, pr, out, s);
+    if (rc) return rc;
+    return ok();
+}
+
+int p2s_debug_noise(int Nfy, int Nfx, int plane, uint64_t seed, uint32_t* raw, float* normals, void* stream) {
+    if (Nfy < 1 || Nfx < 1 || Nfy > 65536 || Nfx > 65536) return fail(P2S_EINVAL, "bad grid %d x %d", Nfy, Nfx);
+    if (plane < 0) return fail(P2S_EINVAL, "plane must be >= 0");
+    if (!raw) return fail(P2S_EINVAL, "raw is NULL");
+    hipError_t e = launch_debug_noise(Nfy, Nfx, plane, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), raw,
+                                      normals, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "noise kernel");
+    return ok();
+}
+
+}  // extern "C"

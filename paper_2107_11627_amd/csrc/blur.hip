@@ -1,0 +1,321 @@
+// Stage 3 of the hot path: the spatially varying blur of Sec. 3.1 in its
+// basis form (Eq. 4-5),
+//
+//   out_c(x) = sum_k w_k(x) * sum_u phi_k(u) I_c(clamp(x - u)),
+//
+// computed per output tile as one GEMM on MFMA followed by a row dot:
+//   conv[k][pixel] = sum_taps basis[k][tap] * patch[tap][pixel]  (MFMA, FP32 acc)
+//   out[pixel]     = sum_k conv[k][pixel] * w[pixel][k]           (epilogue)
+// The K convolution results live only in accumulator registers.
+//
+// A operand = basis (rows: 16 basis functions per block), B operand = image
+// patches (columns: 16 consecutive pixels of one image row), reduction over
+// PSF taps.  The accumulator lane layout (basis 16 mb + 4 (L/16) + i, pixel
+// L%16) lets each lane fold its 4 basis rows per block against w with one
+// float4 load, leaving a 4-way cross-lane sum.
+//
+// Tile: 16 x 32 pixels per workgroup (4 waves, each 4 rows x 32 pixels = 8
+// pixel blocks), or 8 x 32 with 4 pixel blocks per wave when K > 112.
+#include "internal.hpp"
+
+namespace p2s {
+namespace {
+
+constexpr int kTX = 32;
+constexpr int kMaxR = (P2S_MAX_P - 1) / 2;
+
+__device__ __forceinline__ float wave_sum4(float v) {
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// Epilogue shared by both precisions: dot the accumulators with w and store.
+template <int NMB>
+__device__ __forceinline__ void epilogue(const floatx4 acc[NMB], const float* __restrict__ w, int K, int y, int x,
+                                         int H, int W, int g, float* __restrict__ out_c) {
+    float part = 0.0f;
+    const bool valid = (y < H) && (x < W);
+    if (valid) {
+        const float* wp = w + ((size_t)y * W + x) * K;
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb) {
+            const int k = 16 * mb + 4 * g;
+            if ((K & 3) == 0) {
+                if (k < K) {
+                    const float4 wv = *reinterpret_cast<const float4*>(wp + k);
+                    part += acc[mb][0] * wv.x + acc[mb][1] * wv.y + acc[mb][2] * wv.z + acc[mb][3] * wv.w;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (k + i < K) part += acc[mb][i] * wp[k + i];
+            }
+        }
+    }
+    part = wave_sum4(part);
+    if (valid && g == 0) out_c[(size_t)y * W + x] = part;
+}
+
+// ------------------------------------------------------------------ FP32
+// LDS tile of the image with a halo of R on every side (replicate border),
+// pitch padded by one float.  Tap u = 4 t + L/16 in row-major (dy, dx) order.
+template <int NMB, int NBLK>
+__global__ void __launch_bounds__(256) blur_f32_kernel(const float* __restrict__ img, int C, int H, int W, int P,
+                                                       const float* __restrict__ bp, int t4, int K,
+                                                       const float* __restrict__ w, float* __restrict__ out,
+                                                       int tiles_x) {
+    constexpr int TY = NBLK * 2;                  // rows per workgroup: 4 waves x (NBLK/2) rows
+    constexpr int LW = kTX + 2 * kMaxR;
+    constexpr int PITCH = LW + 1;
+    constexpr int LH = TY + 2 * kMaxR;
+    __shared__ float tile[LH * PITCH];
+    const int R = (P - 1) / 2;
+    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    const int x0 = tx * kTX, y0 = ty * TY;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, m = lane & 15;
+    constexpr int RPW = NBLK / 2;                 // rows per wave
+    const int lyw = wave * RPW;
+    const size_t HW = (size_t)H * W;
+    const int th = TY + 2 * R, twd = kTX + 2 * R;
+
+    for (int c = 0; c < C; ++c) {
+        const float* ic = img + c * HW;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < th * twd; idx += blockDim.x) {
+            const int r = idx / twd, q = idx - r * twd;
+            const int yy = min(max(y0 - R + r, 0), H - 1);
+            const int xx = min(max(x0 - R + q, 0), W - 1);
+            tile[r * PITCH + q] = ic[(size_t)yy * W + xx];
+        }
+        __syncthreads();
+        floatx4 acc[NBLK][NMB];
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) acc[b][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        // pixel (lyw + b/2, 16 (b%2) + m) sits at tile (.. + R, .. + R)
+        const int base = (lyw + R) * PITCH + m + R;
+        int dy = g / P - R, dx = g % P - R;
+        // Same two-set operand pipeline as the BF16 kernel.
+        float a0[NMB], p0[NBLK], a1[NMB], p1[NBLK];
+        auto fetch = [&](int t, float* av, float* pv) {
+            const int off = (dy <= R) ? dy * PITCH + dx : 0;
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) av[mb] = bp[((size_t)t * NMB + mb) * 64 + lane];
+#pragma unroll
+            for (int b = 0; b < NBLK; ++b) pv[b] = tile[base + (b >> 1) * PITCH + (b & 1) * 16 + off];
+            dx += 4;
+            while (dx > R) {
+                dx -= P;
+                dy += 1;
+            }
+        };
+        auto mma = [&](const float* av, const float* pv) {
+#pragma unroll
+            for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb)
+                    acc[b][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], pv[b], acc[b][mb], 0, 0, 0);
+        };
+        fetch(0, a0, p0);
+#pragma unroll 1
+        for (int t = 0; t + 1 < t4; t += 2) {
+            fetch(t + 1, a1, p1);
+            mma(a0, p0);
+            fetch(t + 2, a0, p0);
+            mma(a1, p1);
+        }
+        if (t4 & 1) mma(a0, p0);
+        float* oc = out + c * HW;
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b)
+            epilogue<NMB>(acc[b], w, K, y0 + lyw + (b >> 1), x0 + (b & 1) * 16 + m, H, W, g, oc);
+    }
+}
+
+// ------------------------------------------------------------------ BF16
+// Two pre-packed LDS layouts, each entry 8 bf16 (16 bytes), so every B
+// operand is a single aligned ds_read_b128:
+//   RowPk[r][p] = I(y0 - R + r, x0 - R + p + e), e = 0..7   (row chunks)
+//   ColPk[r][q] = I(y0 - R + r + e, x0 + q + R), e = 0..7   (the last tap column)
+// A pixel (ly, lx) reads row chunk (dy, dx0) at RowPk[ly + R + dy][lx + R + dx0]
+// and column chunk q at ColPk[ly + 8 q][lx].  Both share one pitch so that
+// the per-block address delta is the same constant for either kind.
+template <int P, int NMB, int NBLK>
+__global__ void __launch_bounds__(256) blur_bf16_kernel(const float* __restrict__ img, int C, int H, int W,
+                                                        const uint4* __restrict__ bp, int K,
+                                                        const float* __restrict__ w, float* __restrict__ out,
+                                                        int tiles_x) {
+    constexpr int R = (P - 1) / 2;
+    constexpr int A8 = P / 8;                    // row chunks per PSF row
+    constexpr int NROW = P * A8;
+    constexpr int NCOL = (P + 7) / 8;
+    constexpr int T32 = (NROW + NCOL + 3) / 4;
+    constexpr int TY = NBLK * 2;
+    constexpr int PITCH = kTX + 8 * (A8 - 1);    // row-chunk positions per row
+    constexpr int PH = TY + 2 * R;               // rows of RowPk
+    constexpr int QH = TY + 8 * (NCOL - 1);      // rows of ColPk
+    constexpr int NR = PH > QH ? PH : QH;
+    constexpr int SW = kTX + 2 * R;              // fp32 staging tile
+    constexpr int SH = (QH + 7 > PH ? QH + 7 : PH);
+    static_assert(P == 8 * A8 + 1, "bf16 layout needs P = 8a + 1");
+    __shared__ uint4 rowpk[NR * PITCH];
+    __shared__ uint4 colpk[NR * PITCH];
+    __shared__ float stage[SH * SW];
+
+    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    const int x0 = tx * kTX, y0 = ty * TY;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, m = lane & 15;
+    constexpr int RPW = NBLK / 2;
+    const int lyw = wave * RPW;
+    const size_t HW = (size_t)H * W;
+
+    for (int c = 0; c < C; ++c) {
+        const float* ic = img + c * HW;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < SH * SW; idx += blockDim.x) {
+            const int r = idx / SW, q = idx - r * SW;
+            const int yy = min(max(y0 - R + r, 0), H - 1);
+            const int xx = min(max(x0 - R + q, 0), W - 1);
+            stage[idx] = ic[(size_t)yy * W + xx];
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < PH * PITCH; idx += blockDim.x) {
+            const int r = idx / PITCH, p = idx - r * PITCH;
+            const float* s = stage + r * SW + p;
+            uint32_t h[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) h[e] = bf16_bits_rne(s[e]);
+            rowpk[idx] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+        }
+        for (int idx = threadIdx.x; idx < QH * kTX; idx += blockDim.x) {
+            const int r = idx / kTX, q = idx - r * kTX;
+            const float* s = stage + r * SW + q + 2 * R;
+            uint32_t h[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) h[e] = bf16_bits_rne(s[e * SW]);
+            colpk[r * PITCH + q] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+        }
+        __syncthreads();
+        floatx4 acc[NBLK][NMB];
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) acc[b][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const int pbase = lyw * PITCH + m;        // pixel block 0 of this lane
+        // B-operand source of chunk 4 t + g for this lane's pixel block 0
+        auto chunk_src = [&](int t) -> const uint4* {
+            const int ch = 4 * t + g;
+            if (ch < NROW) {
+                const int dy = ch / A8 - R, dx0 = (ch % A8) * 8 - R;
+                return rowpk + pbase + (dy + R) * PITCH + (dx0 + R);
+            }
+            int q = ch - NROW;
+            if (q >= NCOL) q = 0;                 // zero chunk: any valid entry
+            return colpk + pbase + 8 * q * PITCH;
+        };
+        // Two operand sets alternate: the loads of one step are in flight while
+        // the MFMAs of the other run.  Loads one step past the end read a
+        // zero basis step and a valid LDS entry.
+        uint4 a0[NMB], p0[NBLK], a1[NMB], p1[NBLK];
+        auto fetch = [&](int t, uint4* av, uint4* pv) {
+            const uint4* src = chunk_src(t);
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) av[mb] = bp[((size_t)t * NMB + mb) * 64 + lane];
+#pragma unroll
+            for (int b = 0; b < NBLK; ++b) pv[b] = src[(b >> 1) * PITCH + (b & 1) * 16];
+        };
+        auto mma = [&](const uint4* av, const uint4* pv) {
+#pragma unroll
+            for (int b = 0; b < NBLK; ++b) {
+                const bf16x8 px = __builtin_bit_cast(bf16x8, pv[b]);
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb)
+                    acc[b][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[mb]), px,
+                                                                        acc[b][mb], 0, 0, 0);
+            }
+        };
+        fetch(0, a0, p0);
+#pragma unroll 1
+        for (int t = 0; t + 1 < T32; t += 2) {
+            fetch(t + 1, a1, p1);
+            mma(a0, p0);
+            fetch(t + 2, a0, p0);
+            mma(a1, p1);
+        }
+        if constexpr (T32 & 1) mma(a0, p0);
+        float* oc = out + c * HW;
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b)
+            epilogue<NMB>(acc[b], w, K, y0 + lyw + (b >> 1), x0 + (b & 1) * 16 + m, H, W, g, oc);
+    }
+}
+
+template <int NMB>
+hipError_t launch_f32(const Basis& b, const float* img, int C, int H, int W, const float* w, float* out,
+                      hipStream_t s) {
+    constexpr int NBLK = NMB <= 7 ? 8 : 4;
+    constexpr int TY = NBLK * 2;
+    const int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + TY - 1) / TY;
+    hipLaunchKernelGGL((blur_f32_kernel<NMB, NBLK>), dim3(tiles_x * tiles_y), dim3(256), 0, s, img, C, H, W, b.P,
+                       b.f32, b.t4, b.K, w, out, tiles_x);
+    return hipGetLastError();
+}
+
+template <int P, int NMB>
+hipError_t launch_bf16(const Basis& b, const float* img, int C, int H, int W, const float* w, float* out,
+                       hipStream_t s) {
+    constexpr int NBLK = NMB <= 7 ? 8 : 4;
+    constexpr int TY = NBLK * 2;
+    const int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + TY - 1) / TY;
+    hipLaunchKernelGGL((blur_bf16_kernel<P, NMB, NBLK>), dim3(tiles_x * tiles_y), dim3(256), 0, s, img, C, H, W,
+                       reinterpret_cast<const uint4*>(b.bf16), b.K, w, out, tiles_x);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t dispatch_bf16(const Basis& b, const float* img, int C, int H, int W, const float* w, float* out,
+                         hipStream_t s) {
+    switch (b.nmb) {
+        case 1: return launch_bf16<P, 1>(b, img, C, H, W, w, out, s);
+        case 2: return launch_bf16<P, 2>(b, img, C, H, W, w, out, s);
+        case 3: return launch_bf16<P, 3>(b, img, C, H, W, w, out, s);
+        case 4: return launch_bf16<P, 4>(b, img, C, H, W, w, out, s);
+        case 5: return launch_bf16<P, 5>(b, img, C, H, W, w, out, s);
+        case 6: return launch_bf16<P, 6>(b, img, C, H, W, w, out, s);
+        case 7: return launch_bf16<P, 7>(b, img, C, H, W, w, out, s);
+        case 8: return launch_bf16<P, 8>(b, img, C, H, W, w, out, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_blur(const Basis& b, const float* img, int C, int H, int W, const float* w, p2s_precision prec,
+                       float* out, hipStream_t s) {
+    if (prec == P2S_FP32) {
+        switch (b.nmb) {
+            case 1: return launch_f32<1>(b, img, C, H, W, w, out, s);
+            case 2: return launch_f32<2>(b, img, C, H, W, w, out, s);
+            case 3: return launch_f32<3>(b, img, C, H, W, w, out, s);
+            case 4: return launch_f32<4>(b, img, C, H, W, w, out, s);
+            case 5: return launch_f32<5>(b, img, C, H, W, w, out, s);
+            case 6: return launch_f32<6>(b, img, C, H, W, w, out, s);
+            case 7: return launch_f32<7>(b, img, C, H, W, w, out, s);
+            case 8: return launch_f32<8>(b, img, C, H, W, w, out, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (b.P) {
+        case 9: return dispatch_bf16<9>(b, img, C, H, W, w, out, s);
+        case 17: return dispatch_bf16<17>(b, img, C, H, W, w, out, s);
+        case 25: return dispatch_bf16<25>(b, img, C, H, W, w, out, s);
+        case 33: return dispatch_bf16<33>(b, img, C, H, W, w, out, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace p2s

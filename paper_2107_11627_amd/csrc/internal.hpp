@@ -1,0 +1,93 @@
+// Internal declarations of libp2s: handle layouts, kernel launchers and the
+// small device helpers the kernels share.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "p2s.h"
+
+namespace p2s {
+
+// ------------------------------------------------------------------ types
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Device copy of a PSF basis, laid out as MFMA A-operands (rows = basis
+// functions in blocks of 16, reduction = PSF taps).  Taps are stored in
+// correlation order: the operand for tap offset (dy, dx) multiplies the image
+// sample at (y + dy, x + dx) and holds phi_k[R - dy][R - dx].
+struct Basis {
+    int K, P, R;
+    int nmb;              // ceil(K / 16)
+    // FP32: [t4][nmb][64] floats, lane L of step t -> basis 16 mb + L%16,
+    // tap u = 4 t + L/16 in row-major (dy + R, dx + R) order (zero past P*P).
+    int t4;
+    float* f32;
+    // BF16: [t32][nmb][64][8] bf16, chunk c = 4 t + L/16 of 8 taps:
+    //   c <  P*A8          row chunk: dy = c / A8 - R, taps dx = (c % A8) * 8 - R + e
+    //   c <  P*A8 + ncol   column chunk q: taps (dy = -R + 8 q + e, dx = R)
+    //   otherwise          zero
+    // with A8 = P / 8 and ncol = ceil(P / 8); only P = 8 A8 + 1 is laid out.
+    int t32;
+    int bf16_ok;
+    uint16_t* bf16;
+};
+
+struct Mlp {
+    int L;
+    int dims[P2S_MAX_LAYERS + 1];
+    // FP32 A-operands (v_mfma_f32_16x16x4f32): per layer [nmb_out][nkc][64]
+    //   layer 0 chunk kc: lane group g -> input feature 4 kc + g
+    //   layer l > 0 chunk kc = 4 mb' + i: lane group g -> feature 16 mb' + 4 g + i
+    float* w32;
+    size_t off32[P2S_MAX_LAYERS];
+    int nkc32[P2S_MAX_LAYERS];
+    size_t bytes32;
+    // BF16 A-operands (v_mfma_f32_16x16x32_bf16): per layer [nmb_out][nkc][64][8]
+    //   layer 0 chunk kc: lane group g, element e -> feature 32 kc + 8 g + e
+    //   layer l > 0 chunk kc: element e -> feature 16 (2 kc + e / 4) + 4 g + e % 4
+    uint16_t* w16;
+    size_t off16[P2S_MAX_LAYERS];
+    int nkc16[P2S_MAX_LAYERS];
+    size_t bytes16;
+    float* bias;          // per layer, padded to 16 * nmb_out
+    int boff[P2S_MAX_LAYERS];
+};
+
+// ------------------------------------------------------------- launchers
+struct FieldPlan {
+    int H, W, Nfy, Nfx, nplanes;
+    uint32_t k0, k1;
+    float corr_len;
+    float scale_x, scale_y;          // 1 / (sqrt(mean S_x) Nfx), 1 / (sqrt(mean S_y) Nfy)
+    int nrad_x, nrad_y;
+    int rad_x[12], rad_y[12];        // radix passes, product = Nfx / Nfy
+    float sigma[P2S_MAX_ZERNIKE];    // per-plane standard deviation
+};
+
+int factor_radices(int n, int* rad);   // -> number of passes, 0 if not 5-smooth
+hipError_t launch_fields(const FieldPlan& fp, float* T, float* F, hipStream_t s);
+hipError_t launch_debug_noise(int Nfy, int Nfx, int plane, uint32_t k0, uint32_t k1,
+                              uint32_t* raw, float* normals, hipStream_t s);
+hipError_t launch_mlp(const Mlp& m, const float* fields, int H, int W, p2s_precision prec,
+                      float* w, hipStream_t s);
+hipError_t launch_blur(const Basis& b, const float* img, int C, int H, int W, const float* w,
+                       p2s_precision prec, float* out, hipStream_t s);
+hipError_t launch_warp(const float* in, int C, int H, int W, const float* tilt, float scale,
+                       float* out, hipStream_t s);
+
+// --------------------------------------------------------- host helpers
+uint16_t f32_to_bf16_rne(float x);
+
+// ------------------------------------------------------- device helpers
+__device__ __forceinline__ uint32_t bf16_bits_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+}  // namespace p2s

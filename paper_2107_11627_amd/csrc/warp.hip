@@ -1,0 +1,44 @@
+// Stage 4 of the hot path: tilt displacement (Sec. 2.2 and 3.3).  The first
+// two Zernike coefficients shift each pixel after the high-order blur: the
+// output pixel (y, x) samples the blurred image at
+// (y + s alpha_3(y,x), x + s alpha_2(y,x)), s = 2 q / pi pixels per unit tilt
+// coefficient, by bilinear interpolation with the sample position clamped to
+// the image.  Bandwidth bound: one thread per pixel, all channels per thread
+// so the two tilt planes are read once.
+#include "internal.hpp"
+
+namespace p2s {
+namespace {
+
+__global__ void __launch_bounds__(256) warp_kernel(const float* __restrict__ in, int C, int H, int W,
+                                                   const float* __restrict__ tilt, float scale,
+                                                   float* __restrict__ out) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= W || y >= H) return;
+    const size_t HW = (size_t)H * W;
+    const size_t i = (size_t)y * W + x;
+    const float sx = fminf(fmaxf((float)x + scale * tilt[i], 0.0f), (float)(W - 1));
+    const float sy = fminf(fmaxf((float)y + scale * tilt[HW + i], 0.0f), (float)(H - 1));
+    const float fx0 = floorf(sx), fy0 = floorf(sy);
+    const int xa = (int)fx0, ya = (int)fy0;
+    const int xb = min(xa + 1, W - 1), yb = min(ya + 1, H - 1);
+    const float fx = sx - fx0, fy = sy - fy0;
+    for (int c = 0; c < C; ++c) {
+        const float* p = in + c * HW;
+        const float top = (1.0f - fx) * p[(size_t)ya * W + xa] + fx * p[(size_t)ya * W + xb];
+        const float bot = (1.0f - fx) * p[(size_t)yb * W + xa] + fx * p[(size_t)yb * W + xb];
+        out[c * HW + i] = (1.0f - fy) * top + fy * bot;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_warp(const float* in, int C, int H, int W, const float* tilt, float scale, float* out,
+                       hipStream_t s) {
+    dim3 grid((W + 63) / 64, (H + 3) / 4);
+    hipLaunchKernelGGL(warp_kernel, grid, dim3(256), 0, s, in, C, H, W, tilt, scale, out);
+    return hipGetLastError();
+}
+
+}  // namespace p2s
