@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Throughput and latency of the P2S hot path on one MI355X.
+
+A step is one whole frame through the hot path (correlated Zernike fields ->
+P2S network -> fused basis blur -> tilt warp) of the single512 workload:
+512x512, one channel, D/r0 = 3, K = 100 basis PSFs of 33x33, network
+33-100-100-100.  The input image, basis and network are resident in HBM
+before timing starts; every step draws new fields (seed 1000 + step).
+
+Printed: ONE JSON line on stdout (progress goes to stderr) with
+  value        BF16 frames/s (blur and network on BF16 MFMA, FP32 accumulate)
+  fp32         the same for the plain FP32 path
+  latency      p50/p99 single-frame latency, each frame synchronised
+  stages_us    per-stage device time (events around each ABI call)
+  roofline     dominant kernel (BF16 fused blur) against the BF16 MFMA peak
+  cpu_baseline the FP64 oracle timed on this host on a bounded sample, with
+               the GPU outputs' relative L2 error against it
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def blur_flops(C, H, W, K, P):
+    """Algorithmic flops of the fused blur: the K x P^2 tap GEMM per pixel and
+    channel plus the K-term row dot with the weights."""
+    return 2.0 * C * H * W * K * (P * P + 1)
+
+
+def src_digest(*paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_sources):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, only if the kernel sources still match the digest recorded with
+    the counters; else None."""
+    path = os.path.join(ROOT, "profiles", "blur_bf16_single512_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        if rec.get("src_digest") != src_digest(*kernel_sources):
+            return None
+        return float(rec["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--latency-frames", type=int, default=200)
+    ap.add_argument("--stage-reps", type=int, default=20)
+    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (frames are independent and "
+              f"would be routed across GPUs without communication, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import p2s_synth as S
+    from paper_2107_11627_amd import basis as pbasis
+    from paper_2107_11627_amd import p2s
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = S.workload("single512")
+    fr = wl.frames[0]
+    C, H, W, K, P, NZ = fr.C, fr.H, fr.W, wl.K, wl.P, wl.n_zernike
+
+    log(f"[bench] learning the K={K} P={P} basis from {wl.n_psf} PSFs (one-time host setup)")
+    t0 = time.perf_counter()
+    z, d = wl.basis_draws()
+    basis, _ = pbasis.learn_basis(z, d, K, P, NZ)
+    log(f"[bench] basis ready in {time.perf_counter() - t0:.1f} s")
+    Ws, bs = wl.mlp()
+    img_h = fr.image()
+    sim = p2s.Simulator(basis, Ws, bs, n_zernike=NZ)
+    img = torch.from_numpy(img_h).cuda()
+    out = torch.empty_like(img)
+    ws = sim.workspace(C, H, W)
+    stream = torch.cuda.current_stream()
+
+    def frame(seed, prec):
+        p2s.simulate(img, fr.d_over_r0, sim.basis, sim.net, seed, prec, out, ws, NZ)
+
+    res = {}
+    outs = {}
+    for prec in ("bf16", "fp32"):
+        for i in range(args.warmup):
+            frame(1000 + i, prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for i in range(args.steps):
+            frame(1000 + i, prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1)
+        res[prec] = {"frames_per_s": args.steps / (ms / 1e3), "ms_per_frame": ms / args.steps,
+                     "wall_frames_per_s": args.steps / wall}
+        log(f"[bench] {prec}: {res[prec]['frames_per_s']:.1f} frames/s ({ms / args.steps * 1e3:.1f} us/frame)")
+
+        # latency: one frame at a time, synchronised
+        lat_dev, lat_wall = [], []
+        for i in range(args.latency_frames):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t = time.perf_counter()
+            a.record(stream)
+            frame(wl.extra["latency_field_seeds"][i % 200], prec)
+            b.record(stream)
+            b.synchronize()
+            lat_wall.append((time.perf_counter() - t) * 1e3)
+            lat_dev.append(a.elapsed_time(b))
+        res[prec]["latency_ms"] = {"p50": float(np.percentile(lat_dev, 50)), "p99": float(np.percentile(lat_dev, 99)),
+                                   "wall_p50": float(np.percentile(lat_wall, 50)),
+                                   "wall_p99": float(np.percentile(lat_wall, 99))}
+
+        # per-stage device time through the stage-level ABI calls
+        F = ws[:NZ * H * W * 4].view(torch.float32).view(NZ, H, W)
+        wbuf = torch.empty((H * W, K), dtype=torch.float32, device="cuda")
+        fws = torch.empty(p2s.fields_workspace_bytes(H, W, NZ), dtype=torch.uint8, device="cuda")
+        bl = torch.empty_like(img)
+        stages = {"fields": [], "mlp": [], "blur": [], "warp": []}
+        for r in range(args.stage_reps + 2):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            ev[0].record(stream)
+            p2s.make_fields(H, W, fr.d_over_r0, NZ, 1000 + r, F, fws)
+            ev[1].record(stream)
+            p2s.mlp(sim.net, F, NZ, H, W, prec, wbuf)
+            ev[2].record(stream)
+            p2s.blur(img, sim.basis, wbuf, prec, bl)
+            ev[3].record(stream)
+            p2s.warp(bl, F, out)
+            ev[4].record(stream)
+            torch.cuda.synchronize()
+            if r >= 2:
+                for k, name in enumerate(stages):
+                    stages[name].append(ev[k].elapsed_time(ev[k + 1]) * 1e3)
+        res[prec]["stages_us"] = {k: float(np.mean(v)) for k, v in stages.items()}
+        log(f"[bench] {prec} stages (us): " + ", ".join(f"{k} {v:.1f}" for k, v in res[prec]["stages_us"].items()))
+        del wbuf, fws, bl
+
+        frame(fr.field_seed, prec)
+        torch.cuda.synchronize()
+        outs[prec] = out.cpu().numpy().astype(np.float64)
+
+    flops = blur_flops(C, H, W, K, P)
+    blur_s = res["bf16"]["stages_us"]["blur"] * 1e-6
+    achieved = flops / blur_s / 1e12
+    kernel_src = ["paper_2107_11627_amd/csrc/blur.hip", "paper_2107_11627_amd/csrc/internal.hpp"]
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic_from_profiles(kernel_src),
+                "kernel": "blur_bf16_kernel<33,7,8>", "algorithmic_flops_per_launch": flops,
+                "avg_launch_us": blur_s * 1e6, "src_digest": src_digest(*kernel_src)}
+    fp32_blur_s = res["fp32"]["stages_us"]["blur"] * 1e-6
+    fp32_roof = {"bound": "mfma", "achieved": flops / fp32_blur_s / 1e12, "peak": PEAK_FP32_TFLOPS,
+                 "frac": flops / fp32_blur_s / 1e12 / PEAK_FP32_TFLOPS}
+
+    cpu = None
+    errs = None
+    if not args.no_cpu_baseline:
+        from oracle.simulate import simulate as osimulate
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        except Exception:
+            threads = os.cpu_count()
+        log(f"[bench] oracle: {args.cpu_frames} full frames in FP64 on the host ({threads} BLAS threads)")
+        t0 = time.perf_counter()
+        ref = None
+        for i in range(args.cpu_frames):
+            r = osimulate(img_h, fr.d_over_r0, basis, Ws, bs, seed=fr.field_seed + i)["out"]
+            if i == 0:
+                ref = r
+        dt = time.perf_counter() - t0
+        cpu = {"value": args.cpu_frames / dt, "unit": "frames/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"{args.cpu_frames} whole single512 frames (fields, network, blur, warp) in FP64 NumPy",
+               "host_cpus": os.cpu_count()}
+        errs = {p: float(np.linalg.norm(outs[p] - ref) / np.linalg.norm(ref)) for p in outs}
+        log(f"[bench] oracle {cpu['value']:.3f} frames/s; rel-L2 vs oracle: " +
+            ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+
+    line = {
+        "metric": "frames/s at 512^2 K=100 (FP32 vs BF16-MFMA) + p50/p99 frame latency",
+        "value": res["bf16"]["frames_per_s"],
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["bf16"]["ms_per_frame"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "single512: 512x512 C=1 blob image, D/r0=3, 35 Zernike planes, K=100 basis of "
+                               "33x33, network 33-100-100-100, new field seed per frame",
+                   "H": H, "W": W, "C": C, "K": K, "P": P, "n_zernike": NZ, "global_batch": 1},
+        "latency_ms": {"bf16": res["bf16"]["latency_ms"], "fp32": res["fp32"]["latency_ms"]},
+        "fp32": {"frames_per_s": res["fp32"]["frames_per_s"], "ms_per_frame": res["fp32"]["ms_per_frame"],
+                 "blur_roofline": fp32_roof},
+        "stages_us": {"bf16": res["bf16"]["stages_us"], "fp32": res["fp32"]["stages_us"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "rel_l2_vs_oracle": errs,
+        "paper_context": "0.026 s/frame on a Tesla V100 for a 256x256 frame (Table 2); different hardware and frame",
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -130,12 +130,15 @@ int p2s_mlp_info(p2s_mlp_t mlp, int* n_in, int* n_out);
 
 /* ------------------------------------------------------------- compute -- */
 
-/* Stage 1: correlated Zernike fields.  For each plane p (Noll j = p + 2):
- * white noise n_p on the periodic Nf_y x Nf_x grid (p2s_field_grid), drawn
+/* Stage 1: correlated Zernike fields.  Plane p carries Noll mode j = p + 2;
+ * planes 2q and 2q+1 are the real and imaginary parts of one complex field
+ *   G_q(y,x) = (Nf_y Nf_x)^(-1/2) sum_k sqrt(S(k)) n_q(k) e^{+2 pi i k.(y,x)/Nf}
+ * on the periodic Nf_y x Nf_x grid (p2s_field_grid), cropped to the top-left
+ * H x W and scaled by sqrt(V_j (D/r0)^(5/3)).  S(f) = exp(-2 pi^2 l^2 |f|^2)
+ * normalised to mean 1; n_q(k) is complex white noise drawn per frequency bin
  * from Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter
- * (c >> 2, r, p, 0) for cell (r, c), Box-Muller as the oracle documents;
- * filtered by sqrt(S), S(f) = exp(-2 pi^2 l^2 |f|^2) normalised to mean 1;
- * cropped to the top-left H x W and scaled by sqrt(V_j (D/r0)^(5/3)).
+ * (kx, ky, q, 0), Box-Muller on outputs 0 and 1.  Bins where a 1-D factor of
+ * sqrt(S) is below 1e-9 of its peak are skipped (error < 1.5e-9 rms).
  * fields: device float32 [n_zernike][H][W].  ws: device, at least
  * p2s_fields_workspace_bytes.  n_zernike in [1, P2S_MAX_ZERNIKE]. */
 int p2s_make_fields(int H, int W, double D_over_r0, int n_zernike, uint64_t seed,
@@ -174,10 +177,11 @@ int p2s_simulate(const float* image, int C, int H, int W, double D_over_r0, int 
                  p2s_basis_t basis, p2s_mlp_t mlp, uint64_t seed, p2s_precision precision,
                  const p2s_params* params, float* out, void* ws, size_t ws_bytes, void* stream);
 
-/* Test hook: the generator behind p2s_make_fields for one plane.  raw:
- * device uint32 [Nfy][ceil(Nfx/4)][4], the four Philox outputs per counter;
- * normals: device float32 [Nfy][Nfx] (may be NULL). */
-int p2s_debug_noise(int Nfy, int Nfx, int plane, uint64_t seed, uint32_t* raw, float* normals,
+/* Test hook: the noise generator behind p2s_make_fields for plane pair
+ * `pair` on an Nfy x Nfx grid of frequency bins.  raw: device uint32
+ * [Nfy][Nfx][4], the four Philox outputs of counter (kx, ky, pair, 0);
+ * normals: device float32 [Nfy][Nfx][2] (real, imaginary), may be NULL. */
+int p2s_debug_noise(int Nfy, int Nfx, int pair, uint64_t seed, uint32_t* raw, float* normals,
                     void* stream);
 
 #ifdef __cplusplus

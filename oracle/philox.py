@@ -7,14 +7,15 @@ two fixed 32-bit multipliers, and the new counter is
 (hi(M1*x2) ^ x1 ^ k0, lo(M1*x2), hi(M0*x0) ^ x3 ^ k1, lo(M0*x0)); between
 rounds the key is advanced by the two Weyl constants.
 
-Noise layout (a reading; the paper does not fix a generator): the noise value
-of grid cell (r, c) of field plane p under frame seed s uses key
-(s mod 2^32, s >> 32) and counter (c >> 2, r, p, 0).  Cells with c mod 4 in
-{0, 1} use outputs (o0, o1), cells in {2, 3} use (o2, o3); with
-u_a = ((o_a >> 8) + 1) 2^-24 in (0, 1] and u_b = (o_b >> 8) 2^-24 in [0, 1),
-the value is sqrt(-2 ln u_a) cos(2 pi u_b) for even c and the sine for odd c.
+Noise layout (a reading; the paper does not fix a generator): the field
+generator draws its white noise directly in the frequency domain.  Bin
+(ky, kx) of plane pair q under frame seed s uses key (s mod 2^32, s >> 32) and
+counter (kx, ky, q, 0); from outputs o0, o1, with u_a = ((o0 >> 8) + 1) 2^-24
+in (0, 1] and u_b = (o1 >> 8) 2^-24 in [0, 1), the bin's complex normal is
+sqrt(-2 ln u_a) (cos(2 pi u_b) + i sin(2 pi u_b)) -- a Box-Muller pair, so
+real and imaginary parts are independent N(0, 1).  Outputs o2, o3 are unused.
 
-Parity: pinned by a published known-answer vector of Philox4x32-10 and by
+Parity: pinned by published known-answer vectors of Philox4x32-10 and by
 moment tests of the normals.
 """
 import numpy as np
@@ -42,26 +43,20 @@ def philox4x32_10(c0, c1, c2, c3, k0: int, k1: int):
     return tuple(v.astype(np.uint32) for v in (x0, x1, x2, x3))
 
 
-def raw_grid(Nfy: int, Nfx: int, plane: int, seed: int):
-    """The four Philox outputs for every counter (c>>2, r, plane, 0):
-    array [Nfy][ceil(Nfx/4)][4] of uint32."""
-    ng = (Nfx + 3) // 4
-    r = np.arange(Nfy, dtype=np.uint64)[:, None]
-    g = np.arange(ng, dtype=np.uint64)[None, :]
-    o = philox4x32_10(g, r, np.uint64(plane), np.uint64(0), seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+def raw_bins(Nfy: int, Nfx: int, pair: int, seed: int):
+    """The four Philox outputs of counter (kx, ky, pair, 0) for every bin:
+    array [Nfy][Nfx][4] of uint32."""
+    ky = np.arange(Nfy, dtype=np.uint64)[:, None]
+    kx = np.arange(Nfx, dtype=np.uint64)[None, :]
+    o = philox4x32_10(kx, ky, np.uint64(pair), np.uint64(0), seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
     return np.stack(o, axis=-1)
 
 
-def normal_grid(Nfy: int, Nfx: int, plane: int, seed: int) -> np.ndarray:
-    """Standard-normal white noise [Nfy][Nfx] (float64) for one field plane."""
-    raw = raw_grid(Nfy, Nfx, plane, seed)
-    c = np.arange(Nfx)
-    grp = c >> 2
-    hi_pair = (c & 3) >= 2
-    oa = np.where(hi_pair[None, :], raw[:, grp, 2], raw[:, grp, 0]).astype(np.float64)
-    ob = np.where(hi_pair[None, :], raw[:, grp, 3], raw[:, grp, 1]).astype(np.float64)
-    ua = (np.floor(oa / 256.0) + 1.0) * 2.0 ** -24
-    ub = np.floor(ob / 256.0) * 2.0 ** -24
+def complex_normal_bins(Nfy: int, Nfx: int, pair: int, seed: int) -> np.ndarray:
+    """Complex white noise [Nfy][Nfx] (complex128): real and imaginary parts
+    are independent standard normals."""
+    raw = raw_bins(Nfy, Nfx, pair, seed)
+    ua = (np.floor(raw[..., 0].astype(np.float64) / 256.0) + 1.0) * 2.0 ** -24
+    ub = np.floor(raw[..., 1].astype(np.float64) / 256.0) * 2.0 ** -24
     rad = np.sqrt(-2.0 * np.log(ua))
-    odd = (c & 1) == 1
-    return np.where(odd[None, :], rad * np.sin(2.0 * np.pi * ub), rad * np.cos(2.0 * np.pi * ub))
+    return rad * np.cos(2.0 * np.pi * ub) + 1j * rad * np.sin(2.0 * np.pi * ub)

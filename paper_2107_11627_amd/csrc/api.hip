@@ -105,9 +105,25 @@ int read_params(const p2s_params* p, Params* out) {
 // buffers, twiddles and filter): 16 (N|1) + 12 N bytes <= 160 KiB.
 constexpr int kMaxFftLen = 5800;
 
+// Band half-width: the largest k <= N/2 whose 1-D filter factor
+// exp(-pi^2 l^2 (k/N)^2) is still >= 1e-9 of its peak.
+int band_half(int N, double corr_len) {
+    const double a = M_PI * M_PI * corr_len * corr_len;
+    int kc = 0;
+    for (int k = 1; k <= N / 2; ++k) {
+        const double f = (double)k / N;
+        if (std::exp(-a * f * f) >= 1e-9) kc = k;
+        else break;
+    }
+    return kc;
+}
+
+int band_size(int N, double corr_len) { return std::min(N, 2 * band_half(N, corr_len) + 1); }
+
+// Intermediate of the field generator: complex [pairs][H][band columns].
 size_t fields_ws(int H, int W, int nz, const Params& pr) {
-    const int Nfy = grid_of(H, pr.corr_len);
-    return align256((size_t)nz * Nfy * W * sizeof(float));
+    const int Mx = band_size(grid_of(W, pr.corr_len), pr.corr_len);
+    return align256((size_t)((nz + 1) / 2) * H * Mx * 8);
 }
 
 int check_frame(int C, int H, int W) {
@@ -145,9 +161,14 @@ int make_fields_impl(int H, int W, double d, int nz, uint64_t seed, const Params
     fp.nrad_y = factor_radices(fp.Nfy, fp.rad_y);
     if (!fp.nrad_x || !fp.nrad_y) return fail(P2S_EINVAL, "internal: grid not 5-smooth");
     fp.nplanes = nz;
+    fp.npairs = (nz + 1) / 2;
     fp.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
     fp.k1 = (uint32_t)(seed >> 32);
     fp.corr_len = pr.corr_len;
+    fp.kcx = band_half(fp.Nfx, pr.corr_len);
+    fp.kcy = band_half(fp.Nfy, pr.corr_len);
+    fp.Mx = std::min(fp.Nfx, 2 * fp.kcx + 1);
+    fp.My = std::min(fp.Nfy, 2 * fp.kcy + 1);
     const double a = 2.0 * M_PI * M_PI * (double)pr.corr_len * (double)pr.corr_len;
     auto mean_s = [&](int N) {
         double m = 0.0;
@@ -158,8 +179,7 @@ int make_fields_impl(int H, int W, double d, int nz, uint64_t seed, const Params
         }
         return m / N;
     };
-    fp.scale_x = (float)(1.0 / (std::sqrt(mean_s(fp.Nfx)) * fp.Nfx));
-    fp.scale_y = (float)(1.0 / (std::sqrt(mean_s(fp.Nfy)) * fp.Nfy));
+    fp.norm = (float)(1.0 / (std::sqrt(mean_s(fp.Nfx) * mean_s(fp.Nfy)) * std::sqrt((double)fp.Nfx * fp.Nfy)));
     const double d53 = std::pow(d, 5.0 / 3.0);
     for (int p = 0; p < nz; ++p) fp.sigma[p] = (float)std::sqrt(noll_var(p + 2) * d53);
     hipError_t e = launch_fields(fp, (float*)ws, F, s);
@@ -337,7 +357,7 @@ int warp_impl(const float* in, int C, int H, int W, const float* tilt, const Par
     const size_t n = (size_t)C * H * W * 4;
     if (overlap(in, n, out, n)) return fail(P2S_EINVAL, "in and out overlap");
     if (overlap(tilt, (size_t)2 * H * W * 4, out, n)) return fail(P2S_EINVAL, "tilt and out overlap");
-    const float scale = (float)(2.0 * (double)pr.q / M_PI);
+    const double scale = 2.0 * (double)pr.q / M_PI;
     hipError_t e = launch_warp(in, C, H, W, tilt, scale, out, s);
     if (e != hipSuccess) return hip_fail(e, "warp kernel");
     return P2S_OK;
@@ -576,11 +596,12 @@ int p2s_simulate(const float* image, int C, int H, int W, double D_over_r0, int 
     return ok();
 }
 
-int p2s_debug_noise(int Nfy, int Nfx, int plane, uint64_t seed, uint32_t* raw, float* normals, void* stream) {
-    if (Nfy < 1 || Nfx < 1 || Nfy > 65536 || Nfx > 65536) return fail(P2S_EINVAL, "bad grid %d x %d", Nfy, Nfx);
-    if (plane < 0) return fail(P2S_EINVAL, "plane must be >= 0");
+int p2s_debug_noise(int Nfy, int Nfx, int pair, uint64_t seed, uint32_t* raw, float* normals, void* stream) {
+    if (Nfy < 1 || Nfx < 1 || Nfy > 65536 || Nfx > 65536 || (size_t)Nfy * Nfx > ((size_t)1 << 30))
+        return fail(P2S_EINVAL, "bad grid %d x %d", Nfy, Nfx);
+    if (pair < 0) return fail(P2S_EINVAL, "pair must be >= 0");
     if (!raw) return fail(P2S_EINVAL, "raw is NULL");
-    hipError_t e = launch_debug_noise(Nfy, Nfx, plane, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), raw,
+    hipError_t e = launch_debug_noise(Nfy, Nfx, pair, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), raw,
                                       normals, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "noise kernel");
     return ok();

@@ -1,19 +1,23 @@
 // Stage 1 of the hot path: spatially correlated Zernike coefficient planes
 // (the per-pixel alpha_j of Sec. 2.2 Eq. 1, correlated in space as Sec. 3.4
-// requires), made by colouring seeded white noise with a separable Gaussian
-// power spectral density:
+// requires), made by filtering seeded white noise with a Gaussian power
+// spectral density and inverse FFTs.
 //
-//   field_p = crop_HxW( IDFT2( sqrt(S_y) sqrt(S_x) DFT2(noise_p) ) ) * sigma_p
+// The white noise is drawn directly in the frequency domain as i.i.d.
+// complex normals N_q(k) per plane pair q, so that
 //
-// Two passes, each a batch of 1-D complex FFTs held in LDS:
-//   rows:    Philox noise for two grid rows packed as one complex row
-//            (real = row 2q, imag = row 2q+1) -> FFT -> * sqrt(S_x) -> IFFT
-//            -> keep the first W columns -> T[p][r][0..W)
-//   columns: two columns of T packed as one complex column -> FFT ->
-//            * sqrt(S_y) sigma_p -> IFFT -> keep the first H rows -> F[p]
-// The filters are real and even, so the packed real and imaginary parts stay
-// separate exactly.  FFT: Stockham auto-sort, radix 4/2/3/5 passes, twiddles
-// from an FP64-evaluated table in LDS.
+//   G_q(y, x) = (1/sqrt(Nfy Nfx)) sum_k sqrt(S_y(ky) S_x(kx)) N_q(k) e^{+2 pi i k.(y,x)/Nf}
+//
+// and plane 2q = sigma Re G_q, plane 2q+1 = sigma Im G_q (two independent
+// fields per transform).  The Gaussian PSD is negligible away from DC: only
+// the band where the 1-D filter is >= 1e-9 of its peak is kept (the dropped
+// part changes a unit-variance field by < 1.5e-9 rms).  Two kernels:
+//   columns: for each band column kx: noise * filter on the band rows, zero
+//            elsewhere -> inverse FFT along y -> V[q][y][j] for y < H
+//   rows:    for each output row y: V scattered into the band bins -> inverse
+//            FFT along x -> planes 2q, 2q+1 for x < W
+// FFTs: Stockham auto-sort in LDS, radix 4/2/3/5 passes, FP64-evaluated
+// twiddle table, thread -> (transform, butterfly) mapping by shifts.
 #include "internal.hpp"
 
 namespace p2s {
@@ -24,7 +28,6 @@ constexpr int kThreads = 256;
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-// multiply by +i (inv) or -i (forward): the sign of the DFT exponent
 __device__ __forceinline__ float2 mul_i(float2 a, float sgn) {   // sgn * i * a
     return make_float2(-sgn * a.y, sgn * a.x);
 }
@@ -51,10 +54,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
     }
 }
 
-// Four normals for cells 4g .. 4g+3 of grid row r of plane p.
-__device__ __forceinline__ void noise4(int g, int r, int p, uint32_t k0, uint32_t k1, float z[4],
-                                       uint32_t* raw_out = nullptr) {
-    uint32_t c0 = (uint32_t)g, c1 = (uint32_t)r, c2 = (uint32_t)p, c3 = 0u;
+// Complex standard normal of bin (ky, kx) of plane pair q: counter
+// (kx, ky, q, 0), Box-Muller on outputs 0 and 1.
+__device__ __forceinline__ float2 bin_noise(int kx, int ky, int q, uint32_t k0, uint32_t k1,
+                                            uint32_t* raw_out = nullptr) {
+    uint32_t c0 = (uint32_t)kx, c1 = (uint32_t)ky, c2 = (uint32_t)q, c3 = 0u;
     philox4x32_10(c0, c1, c2, c3, k0, k1);
     if (raw_out) {
         raw_out[0] = c0;
@@ -63,33 +67,35 @@ __device__ __forceinline__ void noise4(int g, int r, int p, uint32_t k0, uint32_
         raw_out[3] = c3;
     }
     const float two24 = 5.9604644775390625e-08f;   // 2^-24
-    const float ua0 = (float)((c0 >> 8) + 1u) * two24, ub0 = (float)(c1 >> 8) * two24;
-    const float ua1 = (float)((c2 >> 8) + 1u) * two24, ub1 = (float)(c3 >> 8) * two24;
-    const float r0 = sqrtf(-2.0f * logf(ua0)), r1 = sqrtf(-2.0f * logf(ua1));
-    float s0, co0, s1, co1;
-    sincospif(2.0f * ub0, &s0, &co0);
-    sincospif(2.0f * ub1, &s1, &co1);
-    z[0] = r0 * co0;
-    z[1] = r0 * s0;
-    z[2] = r1 * co1;
-    z[3] = r1 * s1;
+    const float ua = (float)((c0 >> 8) + 1u) * two24, ub = (float)(c1 >> 8) * two24;
+    const float r = sqrtf(-2.0f * logf(ua));
+    float s, c;
+    sincospif(2.0f * ub, &s, &c);
+    return make_float2(r * c, r * s);
 }
 
-// One Stockham pass of radix R over `nfft` transforms of length N stored at
-// stride ld.  Ns = product of the radices already applied.  tw[q] =
-// exp(-2 pi i q / N); sgn = -1 forward, +1 inverse.
+__device__ __forceinline__ int band_to_bin(int j, int kc, int N, int M) { return j <= kc ? j : j + (N - M); }
+
+// One Stockham pass of radix R over 2^lg_nfft transforms of length N stored
+// at stride ld; each transform gets blockDim >> lg_nfft threads.  Ns = product
+// of the radices already applied; tw[q] = exp(-2 pi i q / N); sgn = -1
+// forward, +1 inverse.  j / Ns is formed as floor((j + 0.5) / Ns) in FP32,
+// exact for the sizes here (the fraction stays >= 0.5/Ns from an integer).
 template <int R>
-__device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, float2* __restrict__ dst,
-                                              int N, int ld, int nfft, int Ns, const float2* __restrict__ tw,
+__device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, float2* __restrict__ dst, int N,
+                                              int ld, int lg_nfft, int Ns, const float2* __restrict__ tw,
                                               float sgn) {
     const int nb = N / R;
     const int step = N / (Ns * R);
-    for (int idx = threadIdx.x; idx < nfft * nb; idx += blockDim.x) {
-        const int f = idx / nb;
-        const int j = idx - f * nb;
-        const float2* s = src + f * ld;
-        float2* d = dst + f * ld;
-        const int k = j % Ns;
+    const float inv_ns = 1.0f / (float)Ns;
+    const int lg_tpf = __builtin_ctz(blockDim.x) - lg_nfft;
+    const int f = threadIdx.x >> lg_tpf;
+    const int tpf = 1 << lg_tpf;
+    const float2* s = src + f * ld;
+    float2* d = dst + f * ld;
+    for (int j = threadIdx.x & (tpf - 1); j < nb; j += tpf) {
+        const int qj = __float2int_rd(((float)j + 0.5f) * inv_ns);
+        const int k = j - qj * Ns;
         float2 v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -139,22 +145,22 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
             o[2] = make_float2(p2.x + q2.x, p2.y + q2.y);
             o[3] = make_float2(p2.x - q2.x, p2.y - q2.y);
         }
-        const int base = (j / Ns) * Ns * R + k;
+        const int base = qj * Ns * R + k;
 #pragma unroll
         for (int q = 0; q < R; ++q) d[base + q * Ns] = o[q];
     }
 }
 
-// Full transform; returns the buffer holding the result.
-__device__ float2* fft_batch(float2* a, float2* b, int N, int ld, int nfft, const int* rad, int nrad,
+// Full transform of 2^lg_nfft sequences; returns the buffer with the result.
+__device__ float2* fft_batch(float2* a, float2* b, int N, int ld, int lg_nfft, const int* rad, int nrad,
                              const float2* tw, float sgn) {
     int Ns = 1;
     for (int i = 0; i < nrad; ++i) {
         const int R = rad[i];
-        if (R == 4) stockham_pass<4>(a, b, N, ld, nfft, Ns, tw, sgn);
-        else if (R == 2) stockham_pass<2>(a, b, N, ld, nfft, Ns, tw, sgn);
-        else if (R == 3) stockham_pass<3>(a, b, N, ld, nfft, Ns, tw, sgn);
-        else stockham_pass<5>(a, b, N, ld, nfft, Ns, tw, sgn);
+        if (R == 4) stockham_pass<4>(a, b, N, ld, lg_nfft, Ns, tw, sgn);
+        else if (R == 2) stockham_pass<2>(a, b, N, ld, lg_nfft, Ns, tw, sgn);
+        else if (R == 3) stockham_pass<3>(a, b, N, ld, lg_nfft, Ns, tw, sgn);
+        else stockham_pass<5>(a, b, N, ld, lg_nfft, Ns, tw, sgn);
         __syncthreads();
         float2* t = a;
         a = b;
@@ -164,147 +170,127 @@ __device__ float2* fft_batch(float2* a, float2* b, int N, int ld, int nfft, cons
     return a;
 }
 
-// Twiddle table exp(-2 pi i q / N) (FP64 evaluation) and the real even filter
-// h[k] = exp(-pi^2 l^2 f_k^2) * scale, f_k = k/N wrapped to [-1/2, 1/2).
-__device__ void fill_tables(float2* tw, float* filt, int N, float corr_len, float scale) {
-    const double a = 3.14159265358979323846 * 3.14159265358979323846 * (double)corr_len * (double)corr_len;
+__device__ void fill_twiddles(float2* tw, int N) {
     for (int q = threadIdx.x; q < N; q += blockDim.x) {
         double s, c;
         sincospi(-2.0 * (double)q / (double)N, &s, &c);
         tw[q] = make_float2((float)c, (float)s);
-        const int kk = (q < (N + 1) / 2) ? q : q - N;
-        const double f = (double)kk / (double)N;
-        filt[q] = (float)(exp(-a * f * f) * (double)scale);
     }
+}
+
+// exp(-pi^2 l^2 f^2), f = k/N wrapped to [-1/2, 1/2): the 1-D factor of sqrt(S)
+__device__ __forceinline__ float gauss_filter(int k, int N, float corr_len) {
+    const double a = 3.14159265358979323846 * 3.14159265358979323846 * (double)corr_len * (double)corr_len;
+    const int kk = (k < (N + 1) / 2) ? k : k - N;
+    const double f = (double)kk / (double)N;
+    return (float)exp(-a * f * f);
 }
 
 __device__ __forceinline__ int ld_of(int N) { return N | 1; }   // odd stride spreads LDS banks
 
-__global__ void __launch_bounds__(kThreads) fields_rows_kernel(FieldPlan fp, float* __restrict__ T, int fpb) {
+// Kernel 1: noise spectrum of band columns -> inverse FFT along y.
+__global__ void __launch_bounds__(kThreads) fields_cols_kernel(FieldPlan fp, float2* __restrict__ V, int lg_cpb) {
     extern __shared__ float2 smem[];
-    const int N = fp.Nfx, ld = ld_of(N);
-    float2* buf0 = smem;
-    float2* buf1 = smem + fpb * ld;
-    float2* tw = smem + 2 * fpb * ld;
-    float* filt = reinterpret_cast<float*>(tw + N);
-    const int plane = blockIdx.y;
-    const int pair0 = blockIdx.x * fpb;
-    const int npairs = (fp.Nfy + 1) / 2;
-    fill_tables(tw, filt, N, fp.corr_len, fp.scale_x);
-
-    const int ng = (N + 3) / 4;
-    for (int idx = threadIdx.x; idx < fpb * 2 * ng; idx += blockDim.x) {
-        const int f = idx / (2 * ng);
-        const int rem = idx - f * 2 * ng;
-        const int half = rem / ng;
-        const int g = rem - half * ng;
-        const int r = 2 * (pair0 + f) + half;
-        float z[4] = {0.f, 0.f, 0.f, 0.f};
-        if (r < fp.Nfy) noise4(g, r, plane, fp.k0, fp.k1, z);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int c = 4 * g + e;
-            if (c < N) {
-                float* dst = reinterpret_cast<float*>(&buf0[f * ld + c]);
-                dst[half] = z[e];
-            }
-        }
-    }
-    __syncthreads();
-    float2* X = fft_batch(buf0, buf1, N, ld, fpb, fp.rad_x, fp.nrad_x, tw, -1.0f);
-    float2* Y = (X == buf0) ? buf1 : buf0;
-    for (int idx = threadIdx.x; idx < fpb * N; idx += blockDim.x) {
-        const int f = idx / N, k = idx - f * N;
-        const float h = filt[k];
-        float2 v = X[f * ld + k];
-        X[f * ld + k] = make_float2(v.x * h, v.y * h);
-    }
-    __syncthreads();
-    X = fft_batch(X, Y, N, ld, fpb, fp.rad_x, fp.nrad_x, tw, 1.0f);
-    const int W = fp.W;
-    for (int idx = threadIdx.x; idx < fpb * 2 * W; idx += blockDim.x) {
-        const int f = idx / (2 * W);
-        const int rem = idx - f * 2 * W;
-        const int half = rem / W;
-        const int c = rem - half * W;
-        const int pair = pair0 + f;
-        const int r = 2 * pair + half;
-        if (pair < npairs && r < fp.Nfy) {
-            const float2 v = X[f * ld + c];
-            T[((size_t)plane * fp.Nfy + r) * W + c] = half ? v.y : v.x;
-        }
-    }
-}
-
-__global__ void __launch_bounds__(kThreads) fields_cols_kernel(FieldPlan fp, const float* __restrict__ T,
-                                                               float* __restrict__ F, int fpb) {
-    extern __shared__ float2 smem[];
+    const int cpb = 1 << lg_cpb;
     const int N = fp.Nfy, ld = ld_of(N);
     float2* buf0 = smem;
-    float2* buf1 = smem + fpb * ld;
-    float2* tw = smem + 2 * fpb * ld;
+    float2* buf1 = smem + cpb * ld;
+    float2* tw = smem + 2 * cpb * ld;
     float* filt = reinterpret_cast<float*>(tw + N);
-    const int plane = blockIdx.y;
-    const int c0 = blockIdx.x * 2 * fpb;
-    const int W = fp.W, H = fp.H;
-    fill_tables(tw, filt, N, fp.corr_len, fp.scale_y * fp.sigma[plane]);
-    const int ncol = 2 * fpb;
-    const float* Tp = T + (size_t)plane * N * W;
-    for (int idx = threadIdx.x; idx < N * ncol; idx += blockDim.x) {
-        const int r = idx / ncol;
-        const int j = idx - r * ncol;
-        const int c = c0 + j;
-        const float v = (c < W) ? Tp[(size_t)r * W + c] : 0.0f;
-        float* dst = reinterpret_cast<float*>(&buf0[(j >> 1) * ld + r]);
-        dst[j & 1] = v;
+    const int q = blockIdx.y;
+    const int j0 = blockIdx.x * cpb;
+    fill_twiddles(tw, N);
+    for (int k = threadIdx.x; k < N; k += blockDim.x) filt[k] = gauss_filter(k, N, fp.corr_len);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < cpb * N; idx += blockDim.x) {
+        const int c = idx / N;                 // small: cpb <= 8
+        const int ky = idx - c * N;
+        const int j = j0 + c;
+        const int kyw = ky < (N + 1) / 2 ? ky : N - ky;
+        float2 v = make_float2(0.f, 0.f);
+        if (j < fp.Mx && kyw <= fp.kcy) {
+            const int kx = band_to_bin(j, fp.kcx, fp.Nfx, fp.Mx);
+            const float h = gauss_filter(kx, fp.Nfx, fp.corr_len) * filt[ky] * fp.norm;
+            const float2 z = bin_noise(kx, ky, q, fp.k0, fp.k1);
+            v = make_float2(h * z.x, h * z.y);
+        }
+        buf0[c * ld + ky] = v;
     }
     __syncthreads();
-    float2* X = fft_batch(buf0, buf1, N, ld, fpb, fp.rad_y, fp.nrad_y, tw, -1.0f);
-    float2* Y = (X == buf0) ? buf1 : buf0;
-    for (int idx = threadIdx.x; idx < fpb * N; idx += blockDim.x) {
-        const int f = idx / N, k = idx - f * N;
-        const float h = filt[k];
-        float2 v = X[f * ld + k];
-        X[f * ld + k] = make_float2(v.x * h, v.y * h);
+    const float2* X = fft_batch(buf0, buf1, N, ld, lg_cpb, fp.rad_y, fp.nrad_y, tw, 1.0f);
+    const int H = fp.H, Mx = fp.Mx;
+    float2* Vq = V + (size_t)q * H * Mx;
+    for (int idx = threadIdx.x; idx < H * cpb; idx += blockDim.x) {
+        const int y = idx >> lg_cpb;
+        const int c = idx & (cpb - 1);
+        const int j = j0 + c;
+        if (j < Mx) Vq[(size_t)y * Mx + j] = X[c * ld + y];
+    }
+}
+
+// Kernel 2: band spectrum of output rows -> inverse FFT along x -> two planes.
+__global__ void __launch_bounds__(kThreads) fields_rows_kernel(FieldPlan fp, const float2* __restrict__ V,
+                                                               float* __restrict__ F, int lg_rpb) {
+    extern __shared__ float2 smem[];
+    const int rpb = 1 << lg_rpb;
+    const int N = fp.Nfx, ld = ld_of(N);
+    float2* buf0 = smem;
+    float2* buf1 = smem + rpb * ld;
+    float2* tw = smem + 2 * rpb * ld;
+    const int q = blockIdx.y;
+    const int y0 = blockIdx.x * rpb;
+    const int H = fp.H, W = fp.W, Mx = fp.Mx;
+    fill_twiddles(tw, N);
+    for (int idx = threadIdx.x; idx < rpb * ld; idx += blockDim.x) buf0[idx] = make_float2(0.f, 0.f);
+    __syncthreads();
+    const float2* Vq = V + (size_t)q * H * Mx;
+    for (int idx = threadIdx.x; idx < rpb * Mx; idx += blockDim.x) {
+        const int r = idx / Mx;                // small: rpb <= 8
+        const int j = idx - r * Mx;
+        const int y = y0 + r;
+        if (y < H) buf0[r * ld + band_to_bin(j, fp.kcx, N, Mx)] = Vq[(size_t)y * Mx + j];
     }
     __syncthreads();
-    X = fft_batch(X, Y, N, ld, fpb, fp.rad_y, fp.nrad_y, tw, 1.0f);
-    float* Fp = F + (size_t)plane * H * W;
-    for (int idx = threadIdx.x; idx < H * ncol; idx += blockDim.x) {
-        const int r = idx / ncol;
-        const int j = idx - r * ncol;
-        const int c = c0 + j;
-        if (c < W) {
-            const float2 v = X[(j >> 1) * ld + r];
-            Fp[(size_t)r * W + c] = (j & 1) ? v.y : v.x;
+    const float2* X = fft_batch(buf0, buf1, N, ld, lg_rpb, fp.rad_x, fp.nrad_x, tw, 1.0f);
+    const int p0 = 2 * q, p1 = 2 * q + 1;
+    const float s0 = fp.sigma[p0];
+    const bool has1 = p1 < fp.nplanes;
+    const float s1 = has1 ? fp.sigma[p1] : 0.0f;
+    float* F0 = F + (size_t)p0 * H * W;
+    float* F1 = F + (size_t)p1 * H * W;
+    for (int r = 0; r < rpb; ++r) {
+        const int y = y0 + r;
+        if (y >= H) break;
+        for (int x = threadIdx.x; x < W; x += blockDim.x) {
+            const float2 v = X[r * ld + x];
+            F0[(size_t)y * W + x] = s0 * v.x;
+            if (has1) F1[(size_t)y * W + x] = s1 * v.y;
         }
     }
 }
 
-__global__ void debug_noise_kernel(int Nfy, int Nfx, int plane, uint32_t k0, uint32_t k1, uint32_t* raw,
+__global__ void debug_noise_kernel(int Nfy, int Nfx, int pair, uint32_t k0, uint32_t k1, uint32_t* raw,
                                    float* normals) {
-    const int ng = (Nfx + 3) / 4;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= Nfy * ng) return;
-    const int r = idx / ng, g = idx - r * ng;
-    float z[4];
+    if (idx >= Nfy * Nfx) return;
+    const int ky = idx / Nfx, kx = idx - ky * Nfx;
     uint32_t o[4];
-    noise4(g, r, plane, k0, k1, z, o);
+    const float2 z = bin_noise(kx, ky, pair, k0, k1, o);
 #pragma unroll
     for (int e = 0; e < 4; ++e) raw[(size_t)idx * 4 + e] = o[e];
     if (normals) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (4 * g + e < Nfx) normals[(size_t)r * Nfx + 4 * g + e] = z[e];
+        normals[(size_t)idx * 2] = z.x;
+        normals[(size_t)idx * 2 + 1] = z.y;
     }
 }
 
-size_t fft_lds_bytes(int N, int fpb) { return (size_t)(2 * fpb * (N | 1) + N) * 8 + (size_t)N * 4; }
+size_t cols_lds(int N, int nb) { return (size_t)(2 * nb * (N | 1) + N) * 8 + (size_t)N * 4; }
+size_t rows_lds(int N, int nb) { return (size_t)(2 * nb * (N | 1) + N) * 8; }
 
-int pick_fpb(int N, size_t budget) {
-    int f = 8;
-    while (f > 1 && fft_lds_bytes(N, f) > budget) f >>= 1;
-    return f;
+int pick_lg(int N, size_t budget, size_t (*lds)(int, int)) {
+    int lg = 3;
+    while (lg > 0 && lds(N, 1 << lg) > budget) --lg;
+    return lg;
 }
 
 }  // namespace
@@ -318,37 +304,37 @@ int factor_radices(int n, int* rad) {
     return n == 1 ? k : 0;
 }
 
-hipError_t launch_fields(const FieldPlan& fp, float* T, float* F, hipStream_t s) {
+hipError_t launch_fields(const FieldPlan& fp, float* V, float* F, hipStream_t s) {
     const size_t kMaxLds = 160 * 1024;
-    const int fr = pick_fpb(fp.Nfx, 48 * 1024);
-    const int fc = pick_fpb(fp.Nfy, 80 * 1024);
-    const size_t lr = fft_lds_bytes(fp.Nfx, fr), lc = fft_lds_bytes(fp.Nfy, fc);
-    if (lr > kMaxLds || lc > kMaxLds) return hipErrorInvalidValue;
+    const int lc = pick_lg(fp.Nfy, 96 * 1024, cols_lds);
+    const int lr = pick_lg(fp.Nfx, 48 * 1024, rows_lds);
+    const size_t bc = cols_lds(fp.Nfy, 1 << lc), br = rows_lds(fp.Nfx, 1 << lr);
+    if (bc > kMaxLds || br > kMaxLds) return hipErrorInvalidValue;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)fields_rows_kernel,
+        hipError_t e = hipFuncSetAttribute((const void*)fields_cols_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
         if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void*)fields_cols_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+        e = hipFuncSetAttribute((const void*)fields_rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)kMaxLds);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const int npairs = (fp.Nfy + 1) / 2;
-    dim3 gr((npairs + fr - 1) / fr, fp.nplanes);
-    hipLaunchKernelGGL(fields_rows_kernel, gr, dim3(kThreads), lr, s, fp, T, fr);
+    float2* V2 = reinterpret_cast<float2*>(V);
+    dim3 gc((fp.Mx + (1 << lc) - 1) >> lc, fp.npairs);
+    hipLaunchKernelGGL(fields_cols_kernel, gc, dim3(kThreads), bc, s, fp, V2, lc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 gc((fp.W + 2 * fc - 1) / (2 * fc), fp.nplanes);
-    hipLaunchKernelGGL(fields_cols_kernel, gc, dim3(kThreads), lc, s, fp, (const float*)T, F, fc);
+    dim3 gr((fp.H + (1 << lr) - 1) >> lr, fp.npairs);
+    hipLaunchKernelGGL(fields_rows_kernel, gr, dim3(kThreads), br, s, fp, (const float2*)V2, F, lr);
     return hipGetLastError();
 }
 
-hipError_t launch_debug_noise(int Nfy, int Nfx, int plane, uint32_t k0, uint32_t k1, uint32_t* raw,
+hipError_t launch_debug_noise(int Nfy, int Nfx, int pair, uint32_t k0, uint32_t k1, uint32_t* raw,
                               float* normals, hipStream_t s) {
-    const int n = Nfy * ((Nfx + 3) / 4);
-    hipLaunchKernelGGL(debug_noise_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Nfy, Nfx, plane, k0, k1,
-                       raw, normals);
+    const int n = Nfy * Nfx;
+    hipLaunchKernelGGL(debug_noise_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Nfy, Nfx, pair, k0, k1, raw,
+                       normals);
     return hipGetLastError();
 }
 

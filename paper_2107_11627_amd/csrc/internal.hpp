@@ -59,24 +59,26 @@ struct Mlp {
 
 // ------------------------------------------------------------- launchers
 struct FieldPlan {
-    int H, W, Nfy, Nfx, nplanes;
+    int H, W, Nfy, Nfx, nplanes, npairs;
     uint32_t k0, k1;
     float corr_len;
-    float scale_x, scale_y;          // 1 / (sqrt(mean S_x) Nfx), 1 / (sqrt(mean S_y) Nfy)
+    float norm;                      // 1 / (sqrt(mean S_y mean S_x) sqrt(Nfy Nfx))
+    int kcx, kcy;                    // band half-widths (filter >= 1e-9 of its peak)
+    int Mx, My;                      // band sizes, min(N, 2 kc + 1)
     int nrad_x, nrad_y;
     int rad_x[12], rad_y[12];        // radix passes, product = Nfx / Nfy
     float sigma[P2S_MAX_ZERNIKE];    // per-plane standard deviation
 };
 
 int factor_radices(int n, int* rad);   // -> number of passes, 0 if not 5-smooth
-hipError_t launch_fields(const FieldPlan& fp, float* T, float* F, hipStream_t s);
-hipError_t launch_debug_noise(int Nfy, int Nfx, int plane, uint32_t k0, uint32_t k1,
+hipError_t launch_fields(const FieldPlan& fp, float* V, float* F, hipStream_t s);
+hipError_t launch_debug_noise(int Nfy, int Nfx, int pair, uint32_t k0, uint32_t k1,
                               uint32_t* raw, float* normals, hipStream_t s);
 hipError_t launch_mlp(const Mlp& m, const float* fields, int H, int W, p2s_precision prec,
                       float* w, hipStream_t s);
 hipError_t launch_blur(const Basis& b, const float* img, int C, int H, int W, const float* w,
                        p2s_precision prec, float* out, hipStream_t s);
-hipError_t launch_warp(const float* in, int C, int H, int W, const float* tilt, float scale,
+hipError_t launch_warp(const float* in, int C, int H, int W, const float* tilt, double scale,
                        float* out, hipStream_t s);
 
 // --------------------------------------------------------- host helpers

@@ -4,26 +4,29 @@
 // (y + s alpha_3(y,x), x + s alpha_2(y,x)), s = 2 q / pi pixels per unit tilt
 // coefficient, by bilinear interpolation with the sample position clamped to
 // the image.  Bandwidth bound: one thread per pixel, all channels per thread
-// so the two tilt planes are read once.
+// so the two tilt planes are read once.  The sample position is formed in
+// FP64 so that its rounding does not grow with the pixel index.
 #include "internal.hpp"
 
 namespace p2s {
 namespace {
 
 __global__ void __launch_bounds__(256) warp_kernel(const float* __restrict__ in, int C, int H, int W,
-                                                   const float* __restrict__ tilt, float scale,
+                                                   const float* __restrict__ tilt, double scale,
                                                    float* __restrict__ out) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= W || y >= H) return;
     const size_t HW = (size_t)H * W;
     const size_t i = (size_t)y * W + x;
-    const float sx = fminf(fmaxf((float)x + scale * tilt[i], 0.0f), (float)(W - 1));
-    const float sy = fminf(fmaxf((float)y + scale * tilt[HW + i], 0.0f), (float)(H - 1));
-    const float fx0 = floorf(sx), fy0 = floorf(sy);
+    // Sample position in FP64: in FP32 the rounding of x + d alone is
+    // ulp(x) ~ 1e-5 px on large frames; the interpolation itself stays FP32.
+    const double sx = fmin(fmax((double)x + scale * (double)tilt[i], 0.0), (double)(W - 1));
+    const double sy = fmin(fmax((double)y + scale * (double)tilt[HW + i], 0.0), (double)(H - 1));
+    const double fx0 = floor(sx), fy0 = floor(sy);
     const int xa = (int)fx0, ya = (int)fy0;
     const int xb = min(xa + 1, W - 1), yb = min(ya + 1, H - 1);
-    const float fx = sx - fx0, fy = sy - fy0;
+    const float fx = (float)(sx - fx0), fy = (float)(sy - fy0);
     for (int c = 0; c < C; ++c) {
         const float* p = in + c * HW;
         const float top = (1.0f - fx) * p[(size_t)ya * W + xa] + fx * p[(size_t)ya * W + xb];
@@ -34,7 +37,7 @@ __global__ void __launch_bounds__(256) warp_kernel(const float* __restrict__ in,
 
 }  // namespace
 
-hipError_t launch_warp(const float* in, int C, int H, int W, const float* tilt, float scale, float* out,
+hipError_t launch_warp(const float* in, int C, int H, int W, const float* tilt, double scale, float* out,
                        hipStream_t s) {
     dim3 grid((W + 63) / 64, (H + 3) / 4);
     hipLaunchKernelGGL(warp_kernel, grid, dim3(256), 0, s, in, C, H, W, tilt, scale, out);

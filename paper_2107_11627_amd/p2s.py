@@ -240,12 +240,11 @@ def simulate(image, d_over_r0, basis: Basis, net: Mlp, seed, precision, out, ws,
                               _ptr(ws, name="ws"), ws.numel() * ws.element_size(), _stream(stream)))
 
 
-def debug_noise(Nfy, Nfx, plane, seed, raw, normals=None, stream=None):
+def debug_noise(Nfy, Nfx, pair, seed, raw, normals=None, stream=None):
     import torch
-    ng = (Nfx + 3) // 4
-    _check(lib().p2s_debug_noise(Nfy, Nfx, plane, int(seed) & (2 ** 64 - 1),
-                                 _ptr(raw, torch.int32, (Nfy, ng, 4), "raw"),
-                                 _ptr(normals, torch.float32, (Nfy, Nfx), "normals") if normals is not None else None,
+    _check(lib().p2s_debug_noise(Nfy, Nfx, pair, int(seed) & (2 ** 64 - 1),
+                                 _ptr(raw, torch.int32, (Nfy, Nfx, 4), "raw"),
+                                 _ptr(normals, torch.float32, (Nfy, Nfx, 2), "normals") if normals is not None else None,
                                  _stream(stream)))
 
 

@@ -64,18 +64,18 @@ def oracle_basis(name):
 
 
 # ------------------------------------------------------------------ noise
-@pytest.mark.parametrize("Nfy,Nfx,plane,seed", [(37, 45, 3, (1 << 40) + 7), (8, 4, 0, 0), (576, 576, 34, 11)])
-def test_philox_bitwise_and_normals(p2s, Nfy, Nfx, plane, seed):
-    ng = (Nfx + 3) // 4
-    raw = torch.zeros((Nfy, ng, 4), dtype=torch.int32, device="cuda")
-    nrm = torch.zeros((Nfy, Nfx), dtype=torch.float32, device="cuda")
-    p2s.debug_noise(Nfy, Nfx, plane, seed, raw, nrm)
+@pytest.mark.parametrize("Nfy,Nfx,pair,seed", [(37, 45, 3, (1 << 40) + 7), (8, 4, 0, 0), (576, 576, 17, 11)])
+def test_philox_bitwise_and_normals(p2s, Nfy, Nfx, pair, seed):
+    raw = torch.zeros((Nfy, Nfx, 4), dtype=torch.int32, device="cuda")
+    nrm = torch.zeros((Nfy, Nfx, 2), dtype=torch.float32, device="cuda")
+    p2s.debug_noise(Nfy, Nfx, pair, seed, raw, nrm)
     got = host(raw).view(np.uint32)
-    ref = ophilox.raw_grid(Nfy, Nfx, plane, seed)
+    ref = ophilox.raw_bins(Nfy, Nfx, pair, seed)
     assert np.array_equal(got, ref)
-    zr = ophilox.normal_grid(Nfy, Nfx, plane, seed)
+    zr = ophilox.complex_normal_bins(Nfy, Nfx, pair, seed)
     zg = host(nrm)
-    assert rel_l2(zg, zr) < 1e-6
+    zg = zg[..., 0] + 1j * zg[..., 1]
+    assert rel_l2(np.abs(zg - zr), np.abs(zr) * 0 + 1) < 1e-6 * np.sqrt(2)
     assert np.max(np.abs(zg - zr)) < 2e-5
 
 

@@ -56,9 +56,14 @@ def test_field_grid_matches_oracle(p2s):
 
 def test_workspace_sizes(p2s):
     nf = p2s.field_grid(512)
-    assert p2s.fields_workspace_bytes(512, 512, 35) == ((35 * nf * 512 * 4 + 255) // 256) * 256
+    # band of the Gaussian filter kept by the generator: exp(-pi^2 l^2 (k/N)^2) >= 1e-9
+    kc = max(k for k in range(nf // 2 + 1) if k == 0 or math.exp(-(math.pi * 16.0 * k / nf) ** 2) >= 1e-9)
+    mx = min(nf, 2 * kc + 1)
+    assert kc == 52 and mx == 105
+    v = 18 * 512 * mx * 8
+    assert p2s.fields_workspace_bytes(512, 512, 35) == ((v + 255) // 256) * 256
     ws = p2s.workspace_bytes(1, 512, 512, 35, 100)
-    need = 35 * 512 * 512 * 4 + max(35 * nf * 512 * 4, 512 * 512 * 100 * 4) + 512 * 512 * 4
+    need = 35 * 512 * 512 * 4 + max(v, 512 * 512 * 100 * 4) + 512 * 512 * 4
     assert need <= ws <= need + 3 * 256
     assert p2s.workspace_bytes(0, 512, 512, 35, 100) == 0
     assert p2s.workspace_bytes(1, 512, 512, 35, 200) == 0

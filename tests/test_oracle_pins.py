@@ -219,21 +219,21 @@ def test_grid_size_is_5smooth_with_margin():
         assert fields.grid_size(n, 16.0) == nf
 
 
-def test_fft_filter_equals_circular_convolution():
-    """real(IDFT2(sqrt(S) DFT2(n))) equals brute-force circular convolution of
-    n with g = IDFT2(sqrt(S)) (catches a missing sqrt or a wrong frequency
-    wrap)."""
-    N = 16
-    S = fields.psd(N, N, 1.7)
+def test_colour_equals_brute_force_sum():
+    """G(x) = (1/sqrt(N)) sum_k sqrt(S_k) n_k exp(+2 pi i k.x / Nf), written as
+    a nested loop on a 6 x 5 grid (catches a missing sqrt, a sign of the
+    exponent or a wrong normalisation)."""
+    Ny, Nx = 6, 5
+    S = fields.psd(Ny, Nx, 0.7)
     rng = np.random.default_rng(8)
-    n = rng.normal(size=(N, N))
-    g = np.real(np.fft.ifft2(np.sqrt(S)))
-    ref = np.zeros((N, N))
-    for y in range(N):
-        for x in range(N):
-            for a in range(N):
-                for b in range(N):
-                    ref[y, x] += g[a, b] * n[(y - a) % N, (x - b) % N]
+    n = rng.normal(size=(Ny, Nx)) + 1j * rng.normal(size=(Ny, Nx))
+    ref = np.zeros((Ny, Nx), complex)
+    for y in range(Ny):
+        for x in range(Nx):
+            for ky in range(Ny):
+                for kx in range(Nx):
+                    ref[y, x] += math.sqrt(S[ky, kx]) * n[ky, kx] * np.exp(2j * np.pi * (ky * y / Ny + kx * x / Nx))
+    ref /= math.sqrt(Ny * Nx)
     np.testing.assert_allclose(fields.colour(n, S), ref, atol=1e-12)
 
 
@@ -248,35 +248,38 @@ def test_psd_normalisation_and_covariance_shape():
 
 
 def test_field_statistics_match_target_psd():
-    """Mean periodogram of the periodic coloured noise over many seeds equals
-    S (each bin is exponentially distributed: checked within 4 standard
-    errors in aggregate); the lag covariance equals IDFT(S); different planes
-    are uncorrelated."""
+    """Over many seeds: the mean periodogram of Re G and of Im G equals S
+    (checked per bin within 6 standard errors and in aggregate within 4); the
+    lag covariance of each equals IDFT(S); Re G and Im G, and the fields of two
+    different plane pairs, are uncorrelated."""
     N, ell, M = 32, 3.0, 400
     S = fields.psd(N, N, ell)
-    per = np.zeros((N, N))
-    cov = np.zeros((N, N))
-    cross = 0.0
-    for s in range(M):
-        f = fields.colour(philox.normal_grid(N, N, 0, 1000 + s), S)
-        g = fields.colour(philox.normal_grid(N, N, 1, 1000 + s), S)
-        F = np.fft.fft2(f)
-        per += np.abs(F) ** 2 / (N * N)
-        cov += np.real(np.fft.ifft2(np.abs(F) ** 2)) / (N * N)
-        cross += np.mean(f * g)
-    per /= M
-    cov /= M
-    cross /= M
-    big = S > 1e-3
-    z = (per[big] - S[big]) / (S[big] / math.sqrt(M))
-    assert abs(np.mean(z)) < 4.0 / math.sqrt(big.sum())
-    assert np.max(np.abs(z)) < 6.0
     target = np.real(np.fft.ifft2(S))
+    per = {"re": np.zeros((N, N)), "im": np.zeros((N, N))}
+    cov = {"re": np.zeros((N, N)), "im": np.zeros((N, N))}
+    cross_ri = 0.0
+    cross_pair = 0.0
+    for s in range(M):
+        G = fields.colour(philox.complex_normal_bins(N, N, 0, 1000 + s), S)
+        G2 = fields.colour(philox.complex_normal_bins(N, N, 1, 1000 + s), S)
+        for key, f in (("re", G.real), ("im", G.imag)):
+            F = np.fft.fft2(f)
+            per[key] += np.abs(F) ** 2 / (N * N)
+            cov[key] += np.real(np.fft.ifft2(np.abs(F) ** 2)) / (N * N)
+        cross_ri += np.mean(G.real * G.imag)
+        cross_pair += np.mean(G.real * G2.real)
     # Var of a lag covariance averaged over the N^2 positions of one periodic
     # Gaussian field is at most (2 / N^4) sum_k S_k^2; M seeds divide it by M
     se = math.sqrt(2.0 * np.sum(S ** 2) / N ** 4 / M)
-    assert np.max(np.abs(cov - target)) < 5.0 * se
-    assert abs(cross) < 5.0 * se
+    big = S > 1e-3
+    for key in ("re", "im"):
+        p = per[key] / M
+        z = (p[big] - S[big]) / (S[big] * math.sqrt(2.0 / M))
+        assert abs(np.mean(z)) < 4.0 / math.sqrt(big.sum()), key
+        assert np.max(np.abs(z)) < 6.0, key
+        assert np.max(np.abs(cov[key] / M - target)) < 5.0 * se, key
+    assert abs(cross_ri / M) < 5.0 * se
+    assert abs(cross_pair / M) < 5.0 * se
 
 
 def test_make_fields_scales_and_crops():
@@ -286,7 +289,8 @@ def test_make_fields_scales_and_crops():
     S = fields.psd(Nfy, Nfx, 2.0)
     for p in range(5):
         sig = math.sqrt(noll.noll_variance(p + 2) * 2.0 ** (5 / 3))
-        ref = fields.colour(philox.normal_grid(Nfy, Nfx, p, 77), S)[:H, :W] * sig
+        G = fields.colour(philox.complex_normal_bins(Nfy, Nfx, p // 2, 77), S)[:H, :W]
+        ref = (G.real if p % 2 == 0 else G.imag) * sig
         np.testing.assert_allclose(F[p], ref, atol=1e-14)
 
 
@@ -376,12 +380,14 @@ def test_philox_known_answers(golden):
 
 
 def test_normals_moments():
-    z = philox.normal_grid(512, 512, 3, 12345).ravel()
+    z = philox.complex_normal_bins(512, 512, 3, 12345).ravel()
     n = z.size
-    assert abs(z.mean()) < 4 / math.sqrt(n)
-    assert abs(z.var() - 1) < 4 * math.sqrt(2 / n)
-    k = np.mean(z ** 4)
-    assert abs(k - 3) < 4 * math.sqrt(96 / n)
-    # neighbouring cells (a Box-Muller pair) are uncorrelated
-    zz = philox.normal_grid(256, 256, 0, 7)
-    assert abs(np.mean(zz[:, 0::2] * zz[:, 1::2])) < 4 / math.sqrt(zz.size / 2)
+    for part in (z.real, z.imag):
+        assert abs(part.mean()) < 4 / math.sqrt(n)
+        assert abs(part.var() - 1) < 4 * math.sqrt(2 / n)
+        assert abs(np.mean(part ** 4) - 3) < 4 * math.sqrt(96 / n)
+    # the two halves of a Box-Muller pair are uncorrelated
+    assert abs(np.mean(z.real * z.imag)) < 4 / math.sqrt(n)
+    # neighbouring bins are uncorrelated
+    zz = philox.complex_normal_bins(256, 256, 0, 7)
+    assert abs(np.mean(zz.real[:, 0::2] * zz.real[:, 1::2])) < 4 / math.sqrt(zz.size / 2)
