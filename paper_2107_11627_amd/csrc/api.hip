@@ -254,38 +254,41 @@ int pack_basis(const double* hb, int K, int P, Basis* B) {
 int pack_mlp(int L, const int* dims, const float* const* W, const float* const* b, Mlp* M) {
     M->L = L;
     for (int i = 0; i <= L; ++i) M->dims[i] = dims[i];
+    int mb = 1;
+    for (int l = 1; l <= L; ++l) mb = std::max(mb, (dims[l] + 15) / 16);
+    M->mb = mb;
+    const int mbe = (mb + 1) & ~1;
     std::vector<float> w32, bias;
     std::vector<uint16_t> w16;
     for (int l = 0; l < L; ++l) {
         const int in = dims[l], out = dims[l + 1];
-        const int nmo = (out + 15) / 16;
         const float* Wl = W[l];
         auto wat = [&](int r, int f) -> float { return (r < out && f < in) ? Wl[(size_t)r * in + f] : 0.0f; };
         // FP32
-        const int nkc = (l == 0) ? (in + 3) / 4 : 4 * ((in + 15) / 16);
+        const int nkc = (l == 0) ? (in + 3) / 4 : 4 * mb;
         M->nkc32[l] = nkc;
         M->off32[l] = w32.size() * sizeof(float);
-        for (int mb = 0; mb < nmo; ++mb)
+        for (int ob = 0; ob < mb; ++ob)
             for (int kc = 0; kc < nkc; ++kc)
                 for (int Ln = 0; Ln < 64; ++Ln) {
-                    const int g = Ln / 16, r = 16 * mb + Ln % 16;
+                    const int g = Ln / 16, r = 16 * ob + Ln % 16;
                     const int f = (l == 0) ? 4 * kc + g : 16 * (kc / 4) + 4 * g + kc % 4;
                     w32.push_back(wat(r, f));
                 }
         // BF16
-        const int nk16 = (l == 0) ? (in + 31) / 32 : ((in + 15) / 16 + 1) / 2;
-        M->nkc16[l] = nk16;
+        const int nk16 = (l == 0) ? 2 : mbe / 2;
+        M->nkc16[l] = (l == 0) ? (in + 31) / 32 : nk16;
         M->off16[l] = w16.size() * sizeof(uint16_t);
-        for (int mb = 0; mb < nmo; ++mb)
+        for (int ob = 0; ob < mb; ++ob)
             for (int kc = 0; kc < nk16; ++kc)
                 for (int Ln = 0; Ln < 64; ++Ln)
                     for (int e = 0; e < 8; ++e) {
-                        const int g = Ln / 16, r = 16 * mb + Ln % 16;
+                        const int g = Ln / 16, r = 16 * ob + Ln % 16;
                         const int f = (l == 0) ? 32 * kc + 8 * g + e : 16 * (2 * kc + e / 4) + 4 * g + e % 4;
                         w16.push_back(f32_to_bf16_rne(wat(r, f)));
                     }
         M->boff[l] = (int)bias.size();
-        for (int r = 0; r < 16 * nmo; ++r) bias.push_back((b && b[l] && r < out) ? b[l][r] : 0.0f);
+        for (int r = 0; r < 16 * mb; ++r) bias.push_back((b && b[l] && r < out) ? b[l][r] : 0.0f);
     }
     M->bytes32 = w32.size() * sizeof(float);
     M->bytes16 = w16.size() * sizeof(uint16_t);
@@ -325,6 +328,10 @@ int mlp_impl(const Mlp& m, const float* F, int nz, int H, int W, p2s_precision p
     if (!F || !w) return fail(P2S_EINVAL, "fields or w is NULL");
     int rc = check_prec(prec);
     if (rc) return rc;
+    const size_t wbytes = prec == P2S_FP32 ? m.bytes32 : m.bytes16;
+    if (wbytes > kMlpLdsBytes)
+        return fail(P2S_EUNSUPPORTED, "packed network weights (%zu bytes) exceed the %zu-byte LDS of one workgroup "
+                    "in this precision", wbytes, kMlpLdsBytes);
     const size_t HW = (size_t)H * W;
     if (overlap(F, (size_t)nz * HW * 4, w, HW * m.dims[m.L] * 4)) return fail(P2S_EINVAL, "fields and w overlap");
     // the kernel reads planes 2.. : pass a pointer to plane 2

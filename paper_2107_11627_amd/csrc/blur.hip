@@ -14,8 +14,9 @@
 // L%16) lets each lane fold its 4 basis rows per block against w with one
 // float4 load, leaving a 4-way cross-lane sum.
 //
-// Tile: 16 x 32 pixels per workgroup (4 waves, each 4 rows x 32 pixels = 8
-// pixel blocks), or 8 x 32 with 4 pixel blocks per wave when K > 112.
+// Tile: 16 x 32 pixels of one channel per workgroup (4 waves, each 4 rows x
+// 32 pixels = 8 pixel blocks), or 8 x 32 with 4 pixel blocks per wave when
+// K > 112; grid = tiles x channels.
 #include "internal.hpp"
 
 namespace p2s {
@@ -31,30 +32,84 @@ __device__ __forceinline__ float wave_sum4(float v) {
 }
 
 // Epilogue shared by both precisions: dot the accumulators with w and store.
-template <int NMB>
-__device__ __forceinline__ void epilogue(const floatx4 acc[NMB], const float* __restrict__ w, int K, int y, int x,
-                                         int H, int W, int g, float* __restrict__ out_c) {
-    float part = 0.0f;
-    const bool valid = (y < H) && (x < W);
-    if (valid) {
-        const float* wp = w + ((size_t)y * W + x) * K;
+// The w loads of GB pixel blocks are all issued before any is used (address
+// clamped in bounds, out-of-range terms masked), so one memory round trip
+// serves GB * NMB loads instead of one each.
+template <int NMB, int NBLK>
+__device__ __forceinline__ void epilogue(const floatx4 (&acc)[NBLK][NMB], const float* __restrict__ w, int K,
+                                         int yw, int x0, int H, int W, int g, int m, float* __restrict__ out_c) {
+    constexpr int GB = NBLK < 4 ? NBLK : 4;
 #pragma unroll
-        for (int mb = 0; mb < NMB; ++mb) {
-            const int k = 16 * mb + 4 * g;
+    for (int b0 = 0; b0 < NBLK; b0 += GB) {
+        __builtin_amdgcn_sched_barrier(0);   // keep each batch's loads and sums together
+        float wv[GB][NMB][4];
+#pragma unroll
+        for (int bb = 0; bb < GB; ++bb) {
+            const int b = b0 + bb;
+            const int y = yw + (b >> 1), x = x0 + (b & 1) * 16 + m;
+            const size_t pix = (y < H && x < W) ? (size_t)y * W + x : 0;
+            const float* wp = w + pix * K;
             if ((K & 3) == 0) {
-                if (k < K) {
-                    const float4 wv = *reinterpret_cast<const float4*>(wp + k);
-                    part += acc[mb][0] * wv.x + acc[mb][1] * wv.y + acc[mb][2] * wv.z + acc[mb][3] * wv.w;
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb) {
+                    const int k = 16 * mb + 4 * g;
+                    const float4 v = *reinterpret_cast<const float4*>(wp + (k < K ? k : 0));
+                    wv[bb][mb][0] = v.x;
+                    wv[bb][mb][1] = v.y;
+                    wv[bb][mb][2] = v.z;
+                    wv[bb][mb][3] = v.w;
                 }
             } else {
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (k + i < K) part += acc[mb][i] * wp[k + i];
+                for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int k = 16 * mb + 4 * g + i;
+                        wv[bb][mb][i] = wp[k < K ? k : 0];
+                    }
             }
         }
+#pragma unroll
+        for (int bb = 0; bb < GB; ++bb) {
+            const int b = b0 + bb;
+            const int y = yw + (b >> 1), x = x0 + (b & 1) * 16 + m;
+            float part = 0.0f;
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = 16 * mb + 4 * g + i;
+                    part += (k < K) ? acc[b][mb][i] * wv[bb][mb][i] : 0.0f;
+                }
+            part = wave_sum4(part);
+            if (y < H && x < W && g == 0) out_c[(size_t)y * W + x] = part;
+        }
     }
-    part = wave_sum4(part);
-    if (valid && g == 0) out_c[(size_t)y * W + x] = part;
+}
+
+// Copy a clamped (replicate-border) window of image rows y_lo.. and columns
+// x_lo.. into LDS, nr x nc floats at pitch ld; loads are issued in batches of
+// kBatch per thread before any store.
+template <int kBatch>
+__device__ __forceinline__ void stage_window(float* __restrict__ dst, int ld, const float* __restrict__ ic, int H,
+                                             int W, int y_lo, int x_lo, int nr, int nc) {
+    const int n = nr * nc;
+    for (int base = 0; base < n; base += kBatch * (int)blockDim.x) {
+        float v[kBatch];
+        int at[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int idx = base + i * (int)blockDim.x + (int)threadIdx.x;
+            const int r = idx / nc, q = idx - r * nc;
+            const int yy = min(max(y_lo + r, 0), H - 1);
+            const int xx = min(max(x_lo + q, 0), W - 1);
+            at[i] = idx < n ? r * ld + q : -1;
+            v[i] = ic[(size_t)yy * W + xx];
+        }
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i)
+            if (at[i] >= 0) dst[at[i]] = v[i];
+    }
 }
 
 // ------------------------------------------------------------------ FP32
@@ -71,6 +126,7 @@ __global__ void __launch_bounds__(256) blur_f32_kernel(const float* __restrict__
     constexpr int LH = TY + 2 * kMaxR;
     __shared__ float tile[LH * PITCH];
     const int R = (P - 1) / 2;
+    const int c = blockIdx.y;                     // channel
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
     const int x0 = tx * kTX, y0 = ty * TY;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -80,15 +136,9 @@ __global__ void __launch_bounds__(256) blur_f32_kernel(const float* __restrict__
     const size_t HW = (size_t)H * W;
     const int th = TY + 2 * R, twd = kTX + 2 * R;
 
-    for (int c = 0; c < C; ++c) {
+    {
         const float* ic = img + c * HW;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < th * twd; idx += blockDim.x) {
-            const int r = idx / twd, q = idx - r * twd;
-            const int yy = min(max(y0 - R + r, 0), H - 1);
-            const int xx = min(max(x0 - R + q, 0), W - 1);
-            tile[r * PITCH + q] = ic[(size_t)yy * W + xx];
-        }
+        stage_window<12>(tile, PITCH, ic, H, W, y0 - R, x0 - R, th, twd);
         __syncthreads();
         floatx4 acc[NBLK][NMB];
 #pragma unroll
@@ -128,10 +178,7 @@ __global__ void __launch_bounds__(256) blur_f32_kernel(const float* __restrict__
             mma(a1, p1);
         }
         if (t4 & 1) mma(a0, p0);
-        float* oc = out + c * HW;
-#pragma unroll
-        for (int b = 0; b < NBLK; ++b)
-            epilogue<NMB>(acc[b], w, K, y0 + lyw + (b >> 1), x0 + (b & 1) * 16 + m, H, W, g, oc);
+        epilogue<NMB, NBLK>(acc, w, K, y0 + lyw, x0, H, W, g, m, out + c * HW);
     }
 }
 
@@ -165,6 +212,7 @@ __global__ void __launch_bounds__(256) blur_bf16_kernel(const float* __restrict_
     __shared__ uint4 colpk[NR * PITCH];
     __shared__ float stage[SH * SW];
 
+    const int c = blockIdx.y;                     // channel
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
     const int x0 = tx * kTX, y0 = ty * TY;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -173,15 +221,9 @@ __global__ void __launch_bounds__(256) blur_bf16_kernel(const float* __restrict_
     const int lyw = wave * RPW;
     const size_t HW = (size_t)H * W;
 
-    for (int c = 0; c < C; ++c) {
+    {
         const float* ic = img + c * HW;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < SH * SW; idx += blockDim.x) {
-            const int r = idx / SW, q = idx - r * SW;
-            const int yy = min(max(y0 - R + r, 0), H - 1);
-            const int xx = min(max(x0 - R + q, 0), W - 1);
-            stage[idx] = ic[(size_t)yy * W + xx];
-        }
+        stage_window<14>(stage, SW, ic, H, W, y0 - R, x0 - R, SH, SW);
         __syncthreads();
         for (int idx = threadIdx.x; idx < PH * PITCH; idx += blockDim.x) {
             const int r = idx / PITCH, p = idx - r * PITCH;
@@ -247,10 +289,7 @@ __global__ void __launch_bounds__(256) blur_bf16_kernel(const float* __restrict_
             mma(a1, p1);
         }
         if constexpr (T32 & 1) mma(a0, p0);
-        float* oc = out + c * HW;
-#pragma unroll
-        for (int b = 0; b < NBLK; ++b)
-            epilogue<NMB>(acc[b], w, K, y0 + lyw + (b >> 1), x0 + (b & 1) * 16 + m, H, W, g, oc);
+        epilogue<NMB, NBLK>(acc, w, K, y0 + lyw, x0, H, W, g, m, out + c * HW);
     }
 }
 
@@ -260,7 +299,7 @@ hipError_t launch_f32(const Basis& b, const float* img, int C, int H, int W, con
     constexpr int NBLK = NMB <= 7 ? 8 : 4;
     constexpr int TY = NBLK * 2;
     const int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + TY - 1) / TY;
-    hipLaunchKernelGGL((blur_f32_kernel<NMB, NBLK>), dim3(tiles_x * tiles_y), dim3(256), 0, s, img, C, H, W, b.P,
+    hipLaunchKernelGGL((blur_f32_kernel<NMB, NBLK>), dim3(tiles_x * tiles_y, C), dim3(256), 0, s, img, C, H, W, b.P,
                        b.f32, b.t4, b.K, w, out, tiles_x);
     return hipGetLastError();
 }
@@ -271,7 +310,7 @@ hipError_t launch_bf16(const Basis& b, const float* img, int C, int H, int W, co
     constexpr int NBLK = NMB <= 7 ? 8 : 4;
     constexpr int TY = NBLK * 2;
     const int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + TY - 1) / TY;
-    hipLaunchKernelGGL((blur_bf16_kernel<P, NMB, NBLK>), dim3(tiles_x * tiles_y), dim3(256), 0, s, img, C, H, W,
+    hipLaunchKernelGGL((blur_bf16_kernel<P, NMB, NBLK>), dim3(tiles_x * tiles_y, C), dim3(256), 0, s, img, C, H, W,
                        reinterpret_cast<const uint4*>(b.bf16), b.K, w, out, tiles_x);
     return hipGetLastError();
 }

@@ -39,23 +39,27 @@ struct Basis {
 struct Mlp {
     int L;
     int dims[P2S_MAX_LAYERS + 1];
-    // FP32 A-operands (v_mfma_f32_16x16x4f32): per layer [nmb_out][nkc][64]
+    int mb;               // every layer's output padded to mb blocks of 16
+    // FP32 A-operands (v_mfma_f32_16x16x4f32): per layer [mb][nkc][64]
     //   layer 0 chunk kc: lane group g -> input feature 4 kc + g
     //   layer l > 0 chunk kc = 4 mb' + i: lane group g -> feature 16 mb' + 4 g + i
     float* w32;
     size_t off32[P2S_MAX_LAYERS];
     int nkc32[P2S_MAX_LAYERS];
     size_t bytes32;
-    // BF16 A-operands (v_mfma_f32_16x16x32_bf16): per layer [nmb_out][nkc][64][8]
-    //   layer 0 chunk kc: lane group g, element e -> feature 32 kc + 8 g + e
+    // BF16 A-operands (v_mfma_f32_16x16x32_bf16): per layer [mb][nkc][64][8]
+    //   layer 0 chunk kc (2 chunks): lane group g, element e -> feature 32 kc + 8 g + e
     //   layer l > 0 chunk kc: element e -> feature 16 (2 kc + e / 4) + 4 g + e % 4
     uint16_t* w16;
     size_t off16[P2S_MAX_LAYERS];
     int nkc16[P2S_MAX_LAYERS];
     size_t bytes16;
-    float* bias;          // per layer, padded to 16 * nmb_out
+    float* bias;          // per layer, padded to 16 * mb
     int boff[P2S_MAX_LAYERS];
 };
+
+// Packed network weights are staged in the LDS of one workgroup.
+constexpr size_t kMlpLdsBytes = 160 * 1024;
 
 // ------------------------------------------------------------- launchers
 struct FieldPlan {

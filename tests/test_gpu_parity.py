@@ -75,7 +75,7 @@ def test_philox_bitwise_and_normals(p2s, Nfy, Nfx, pair, seed):
     zr = ophilox.complex_normal_bins(Nfy, Nfx, pair, seed)
     zg = host(nrm)
     zg = zg[..., 0] + 1j * zg[..., 1]
-    assert rel_l2(np.abs(zg - zr), np.abs(zr) * 0 + 1) < 1e-6 * np.sqrt(2)
+    assert np.linalg.norm(zg - zr) / np.linalg.norm(zr) < 1e-6
     assert np.max(np.abs(zg - zr)) < 2e-5
 
 
@@ -128,6 +128,12 @@ def test_mlp(p2s, dims, HW, bias, prec):
     net = p2s.Mlp(Ws, bs)
     Fh = synthetic_fields(nz, H, W, seed=H * W)
     w = torch.full((H * W, dims[-1]), float("nan"), dtype=torch.float32, device="cuda")
+    if prec == "fp32" and len(dims) == 5:
+        # 3 x 128x128 FP32 layers do not fit the 160 KiB LDS of one workgroup
+        with pytest.raises(p2s.P2SError) as e:
+            p2s.mlp(net, dev(Fh), nz, H, W, prec, w)
+        assert e.value.code == p2s.P2S_EUNSUPPORTED
+        return
     p2s.mlp(net, dev(Fh), nz, H, W, prec, w)
     ref = omlp.forward(Ws, bs, np.moveaxis(Fh[2:], 0, -1).reshape(H * W, nz - 2))
     tol = 1e-6 if prec == "fp32" else 1e-4
