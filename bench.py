@@ -67,6 +67,51 @@ def traffic_from_profiles(kernel_sources):
         return None
 
 
+def copy_mode(args, torch):
+    """A plain device-to-device copy of 256 MiB, args.steps times: the bytes
+    read and written per launch are known exactly."""
+    n = 64 << 20
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / args.steps
+    print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                      "avg_us": us, "GBps": 8 * n / us / 1e3}), flush=True)
+
+
+def blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C):
+    """Only the fused blur of the workload, args.steps launches, on weights
+    from one network evaluation."""
+    F = torch.empty((NZ, H, W), dtype=torch.float32, device="cuda")
+    fws = torch.empty(p2s.fields_workspace_bytes(H, W, NZ), dtype=torch.uint8, device="cuda")
+    wbuf = torch.empty((H * W, K), dtype=torch.float32, device="cuda")
+    bl = torch.empty_like(img)
+    p2s.make_fields(H, W, fr.d_over_r0, NZ, fr.field_seed, F, fws)
+    p2s.mlp(sim.net, F, NZ, H, W, args.precision, wbuf)
+    for _ in range(args.warmup):
+        p2s.blur(img, sim.basis, wbuf, args.precision, bl)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        p2s.blur(img, sim.basis, wbuf, args.precision, bl)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / args.steps
+    fl = blur_flops(C, H, W, K, P)
+    print(json.dumps({"mode": "blur", "precision": args.precision, "avg_us": us,
+                      "TFLOPs": fl / us / 1e6, "algorithmic_flops_per_launch": fl,
+                      "algorithmic_bytes_per_launch": 4 * (2 * C * H * W + H * W * K)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +121,10 @@ def main():
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=["frame", "blur", "copy"], default="frame",
+                    help="frame: the benchmark; blur: only the fused blur of the workload (for counter runs); "
+                         "copy: a plain device copy of known size (calibrates byte counters)")
+    ap.add_argument("--precision", choices=["bf16", "fp32"], default="bf16", help="precision of --mode blur")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (frames are independent and "
@@ -89,6 +138,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.mode == "copy":
+        return copy_mode(args, torch)
     wl = S.workload("single512")
     fr = wl.frames[0]
     C, H, W, K, P, NZ = fr.C, fr.H, fr.W, wl.K, wl.P, wl.n_zernike
@@ -108,6 +159,9 @@ def main():
 
     def frame(seed, prec):
         p2s.simulate(img, fr.d_over_r0, sim.basis, sim.net, seed, prec, out, ws, NZ)
+
+    if args.mode == "blur":
+        return blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C)
 
     res = {}
     outs = {}

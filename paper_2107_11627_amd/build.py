@@ -20,6 +20,9 @@ ARCH = os.environ.get("P2S_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # let the register allocator place MFMA accumulators in VGPRs or AGPRs
+    # (with AGPR-only accumulators the large blur tiles spill)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-I", os.path.join(ROOT, "include"), "-I", SRC,
 ]
 
