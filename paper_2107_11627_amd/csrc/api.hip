@@ -120,10 +120,12 @@ int band_half(int N, double corr_len) {
 
 int band_size(int N, double corr_len) { return std::min(N, 2 * band_half(N, corr_len) + 1); }
 
-// Intermediate of the field generator: complex [pairs][H][band columns].
+// Intermediate of the field generator: complex [pairs][H][band columns],
+// followed by the Nfx twiddle factors of the row transforms.
 size_t fields_ws(int H, int W, int nz, const Params& pr) {
-    const int Mx = band_size(grid_of(W, pr.corr_len), pr.corr_len);
-    return align256((size_t)((nz + 1) / 2) * H * Mx * 8);
+    const int Nfx = grid_of(W, pr.corr_len);
+    const int Mx = band_size(Nfx, pr.corr_len);
+    return align256(((size_t)((nz + 1) / 2) * H * Mx + Nfx) * 8);
 }
 
 int check_frame(int C, int H, int W) {

@@ -189,7 +189,8 @@ __device__ __forceinline__ float gauss_filter(int k, int N, float corr_len) {
 __device__ __forceinline__ int ld_of(int N) { return N | 1; }   // odd stride spreads LDS banks
 
 // Kernel 1: noise spectrum of band columns -> inverse FFT along y.
-__global__ void __launch_bounds__(kThreads) fields_cols_kernel(FieldPlan fp, float2* __restrict__ V, int lg_cpb) {
+__global__ void __launch_bounds__(kThreads) fields_cols_kernel(FieldPlan fp, float2* __restrict__ V, int lg_cpb,
+                                                               float2* __restrict__ twx_out) {
     extern __shared__ float2 smem[];
     const int cpb = 1 << lg_cpb;
     const int N = fp.Nfy, ld = ld_of(N);
@@ -199,6 +200,13 @@ __global__ void __launch_bounds__(kThreads) fields_cols_kernel(FieldPlan fp, flo
     float* filt = reinterpret_cast<float*>(tw + N);
     const int q = blockIdx.y;
     const int j0 = blockIdx.x * cpb;
+    if (blockIdx.x == 0 && blockIdx.y == 0) {   // the row kernel's twiddles, evaluated once
+        for (int k = threadIdx.x; k < fp.Nfx; k += blockDim.x) {
+            double sn, cs;
+            sincospi(-2.0 * (double)k / (double)fp.Nfx, &sn, &cs);
+            twx_out[k] = make_float2((float)cs, (float)sn);
+        }
+    }
     fill_twiddles(tw, N);
     for (int k = threadIdx.x; k < N; k += blockDim.x) filt[k] = gauss_filter(k, N, fp.corr_len);
     __syncthreads();
@@ -230,7 +238,8 @@ __global__ void __launch_bounds__(kThreads) fields_cols_kernel(FieldPlan fp, flo
 
 // Kernel 2: band spectrum of output rows -> inverse FFT along x -> two planes.
 __global__ void __launch_bounds__(kThreads) fields_rows_kernel(FieldPlan fp, const float2* __restrict__ V,
-                                                               float* __restrict__ F, int lg_rpb) {
+                                                               float* __restrict__ F, int lg_rpb,
+                                                               const float2* __restrict__ twx) {
     extern __shared__ float2 smem[];
     const int rpb = 1 << lg_rpb;
     const int N = fp.Nfx, ld = ld_of(N);
@@ -240,7 +249,7 @@ __global__ void __launch_bounds__(kThreads) fields_rows_kernel(FieldPlan fp, con
     const int q = blockIdx.y;
     const int y0 = blockIdx.x * rpb;
     const int H = fp.H, W = fp.W, Mx = fp.Mx;
-    fill_twiddles(tw, N);
+    for (int k = threadIdx.x; k < N; k += blockDim.x) tw[k] = twx[k];
     for (int idx = threadIdx.x; idx < rpb * ld; idx += blockDim.x) buf0[idx] = make_float2(0.f, 0.f);
     __syncthreads();
     const float2* Vq = V + (size_t)q * H * Mx;
@@ -321,12 +330,14 @@ hipError_t launch_fields(const FieldPlan& fp, float* V, float* F, hipStream_t s)
         attr = true;
     }
     float2* V2 = reinterpret_cast<float2*>(V);
+    float2* twx = V2 + (size_t)fp.npairs * fp.H * fp.Mx;   // Nfx twiddles after the intermediate
     dim3 gc((fp.Mx + (1 << lc) - 1) >> lc, fp.npairs);
-    hipLaunchKernelGGL(fields_cols_kernel, gc, dim3(kThreads), bc, s, fp, V2, lc);
+    hipLaunchKernelGGL(fields_cols_kernel, gc, dim3(kThreads), bc, s, fp, V2, lc, twx);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 gr((fp.H + (1 << lr) - 1) >> lr, fp.npairs);
-    hipLaunchKernelGGL(fields_rows_kernel, gr, dim3(kThreads), br, s, fp, (const float2*)V2, F, lr);
+    hipLaunchKernelGGL(fields_rows_kernel, gr, dim3(kThreads), br, s, fp, (const float2*)V2, F, lr,
+                       (const float2*)twx);
     return hipGetLastError();
 }
 

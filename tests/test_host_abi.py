@@ -60,7 +60,7 @@ def test_workspace_sizes(p2s):
     kc = max(k for k in range(nf // 2 + 1) if k == 0 or math.exp(-(math.pi * 16.0 * k / nf) ** 2) >= 1e-9)
     mx = min(nf, 2 * kc + 1)
     assert kc == 52 and mx == 105
-    v = 18 * 512 * mx * 8
+    v = (18 * 512 * mx + nf) * 8
     assert p2s.fields_workspace_bytes(512, 512, 35) == ((v + 255) // 256) * 256
     ws = p2s.workspace_bytes(1, 512, 512, 35, 100)
     need = 35 * 512 * 512 * 4 + max(v, 512 * 512 * 100 * 4) + 512 * 512 * 4
