@@ -177,6 +177,80 @@ int p2s_simulate(const float* image, int C, int H, int W, double D_over_r0, int 
                  p2s_basis_t basis, p2s_mlp_t mlp, uint64_t seed, p2s_precision precision,
                  const p2s_params* params, float* out, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------- batches --
+ * Many frames, of any sizes and channel counts, through the same four stages
+ * as p2s_simulate, with one launch per stage for the whole batch: every
+ * workgroup strides over a flat list of (frame, work item) pairs read from a
+ * device-side plan.  Frame i of a batch gives exactly the result
+ * p2s_simulate gives for it alone (same seed, D/r0, handles, precision and
+ * parameters): the stages do the same arithmetic, only the schedule differs.
+ *
+ * Use: p2s_batch_workspace_bytes -> p2s_batch_create (host only, validates
+ * everything and builds the plan) -> p2s_batch_upload (enqueues the copy of
+ * the plan into the workspace) -> p2s_batch_launch (enqueues the kernels;
+ * the only step that may be captured into a HIP graph, and replayed as often
+ * as the plan is unchanged) -> p2s_batch_destroy.  p2s_simulate_batch does
+ * all of it in one call. */
+
+/* One frame of a batch.  image, out: device float32 [C][H][W]. */
+typedef struct {
+    const float* image;
+    float* out;
+    int C, H, W;
+    double D_over_r0;
+    uint64_t seed;
+} p2s_frame;
+
+/* Schedule options of a batch; NULL = the defaults shown. */
+typedef struct {
+    int blur_tile_rows;  /* 16: output rows per blur work item (16 or 8; 8 is
+                            used anyway when the basis has K > 112)          */
+    int persistent;      /* 1: launch as many workgroups as the device holds
+                            at once, each striding over the items; 0: one
+                            workgroup per item                               */
+} p2s_batch_options;
+
+typedef struct p2s_batch_s* p2s_batch_t;
+
+/* Device bytes of workspace a batch needs: the plan, then per frame the same
+ * pieces as p2s_workspace_bytes.  0 on a bad argument (n = 0 gives 0). */
+size_t p2s_batch_workspace_bytes(const p2s_frame* frames, int n, int n_zernike, int K,
+                                 const p2s_params* params);
+
+/* Validate a batch of n >= 0 frames (host: `frames`, read during the call
+ * only) and build its plan in host memory.  Every frame satisfies what
+ * p2s_simulate requires; output buffers must not overlap each other or ws;
+ * images must not overlap ws.  basis and mlp must outlive the batch handle.
+ * ws: device, at least p2s_batch_workspace_bytes; it holds the plan and all
+ * intermediates, and is bound to the handle.  *out receives the handle. */
+int p2s_batch_create(const p2s_frame* frames, int n, int n_zernike, p2s_basis_t basis, p2s_mlp_t mlp,
+                     p2s_precision precision, const p2s_params* params,
+                     const p2s_batch_options* options, void* ws, size_t ws_bytes, p2s_batch_t* out);
+
+/* Enqueue the copy of the plan into the workspace on `stream`.  Needed once
+ * before the first launch (and again after anything else wrote ws).
+ * EUNSUPPORTED while the stream is being captured. */
+int p2s_batch_upload(p2s_batch_t batch, void* stream);
+
+/* Enqueue the batched kernels (fields, network, blur, warp) on `stream`; no
+ * allocation, copy or host synchronisation, so it may be captured. */
+int p2s_batch_launch(p2s_batch_t batch, void* stream);
+
+/* Work items and launched workgroups of the five batched kernels (column and
+ * row field transforms, network, blur, warp); either pointer may be NULL,
+ * otherwise it receives 5 ints. */
+int p2s_batch_info(p2s_batch_t batch, int* items, int* grid);
+
+/* Free the handle; blocks until a pending plan upload has been consumed. */
+int p2s_batch_destroy(p2s_batch_t batch);
+
+/* create + upload + launch + destroy with default options.  Returns once the
+ * plan upload has been consumed on `stream` (that is, after the work queued
+ * on the stream before this call), with the kernels enqueued. */
+int p2s_simulate_batch(const p2s_frame* frames, int n, int n_zernike, p2s_basis_t basis, p2s_mlp_t mlp,
+                       p2s_precision precision, const p2s_params* params, void* ws, size_t ws_bytes,
+                       void* stream);
+
 /* Test hook: the noise generator behind p2s_make_fields for plane pair
  * `pair` on an Nfy x Nfx grid of frequency bins.  raw: device uint32
  * [Nfy][Nfx][4], the four Philox outputs of counter (kx, ky, pair, 0);

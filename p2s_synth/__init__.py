@@ -63,8 +63,9 @@ def blob_image(H: int, W: int, C: int, seed: int, n_blobs: int = 20,
         sg = rng.uniform(sigma_range[0], sigma_range[1], n_blobs)
         am = rng.uniform(amp_range[0], amp_range[1], n_blobs)
         img = np.zeros((H, W), dtype=np.float64)
-        for b in range(n_blobs):
-            img += am[b] * np.exp(-((yy - cy[b]) ** 2 + (xx - cx[b]) ** 2) / (2.0 * sg[b] ** 2))
+        for b in range(n_blobs):   # separable: exp(-(dy^2 + dx^2)/2s^2) = g(dy) g(dx)
+            s2 = 2.0 * sg[b] ** 2
+            img += (am[b] * np.exp(-(yy - cy[b]) ** 2 / s2)) * np.exp(-(xx - cx[b]) ** 2 / s2)
         lo, hi = img.min(), img.max()
         out[c] = (img - lo) / (hi - lo) if hi > lo else np.zeros_like(img)
     if noise_std > 0.0:

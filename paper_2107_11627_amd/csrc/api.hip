@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <limits>
 #include <new>
@@ -18,6 +19,7 @@ struct p2s_basis_s {
 struct p2s_mlp_s {
     p2s::Mlp m;
 };
+
 
 namespace p2s {
 namespace {
@@ -141,14 +143,12 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
     return pa < pb + nb && pb < pa + na;
 }
 
-int make_fields_impl(int H, int W, double d, int nz, uint64_t seed, const Params& pr, float* F, void* ws,
-                     size_t ws_bytes, hipStream_t s) {
+// Plan of the field generator for one frame (validated; no device work).
+int build_field_plan(int H, int W, double d, int nz, uint64_t seed, const Params& pr, FieldPlan* out) {
     if (H < 1 || W < 1 || H > P2S_MAX_SIDE || W > P2S_MAX_SIDE)
         return fail(P2S_EINVAL, "H, W must be in [1, %d], got %d x %d", P2S_MAX_SIDE, H, W);
     if (nz < 1 || nz > P2S_MAX_ZERNIKE) return fail(P2S_EINVAL, "n_zernike must be in [1, %d], got %d", P2S_MAX_ZERNIKE, nz);
     if (!(std::isfinite(d) && d >= 0.0)) return fail(P2S_EINVAL, "D/r0 must be finite and >= 0, got %g", d);
-    if (!F) return fail(P2S_EINVAL, "fields is NULL");
-    if (!ws) return fail(P2S_EINVAL, "workspace is NULL");
     FieldPlan fp{};
     fp.H = H;
     fp.W = W;
@@ -157,8 +157,6 @@ int make_fields_impl(int H, int W, double d, int nz, uint64_t seed, const Params
     if (fp.Nfy > kMaxFftLen || fp.Nfx > kMaxFftLen)
         return fail(P2S_EUNSUPPORTED, "noise grid %d x %d exceeds the single-workgroup FFT limit %d", fp.Nfy, fp.Nfx,
                     kMaxFftLen);
-    const size_t need = fields_ws(H, W, nz, pr);
-    if (ws_bytes < need) return fail(P2S_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     fp.nrad_x = factor_radices(fp.Nfx, fp.rad_x);
     fp.nrad_y = factor_radices(fp.Nfy, fp.rad_y);
     if (!fp.nrad_x || !fp.nrad_y) return fail(P2S_EINVAL, "internal: grid not 5-smooth");
@@ -184,6 +182,19 @@ int make_fields_impl(int H, int W, double d, int nz, uint64_t seed, const Params
     fp.norm = (float)(1.0 / (std::sqrt(mean_s(fp.Nfx) * mean_s(fp.Nfy)) * std::sqrt((double)fp.Nfx * fp.Nfy)));
     const double d53 = std::pow(d, 5.0 / 3.0);
     for (int p = 0; p < nz; ++p) fp.sigma[p] = (float)std::sqrt(noll_var(p + 2) * d53);
+    *out = fp;
+    return P2S_OK;
+}
+
+int make_fields_impl(int H, int W, double d, int nz, uint64_t seed, const Params& pr, float* F, void* ws,
+                     size_t ws_bytes, hipStream_t s) {
+    FieldPlan fp;
+    int rc = build_field_plan(H, W, d, nz, seed, pr, &fp);
+    if (rc) return rc;
+    if (!F) return fail(P2S_EINVAL, "fields is NULL");
+    if (!ws) return fail(P2S_EINVAL, "workspace is NULL");
+    const size_t need = fields_ws(H, W, nz, pr);
+    if (ws_bytes < need) return fail(P2S_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     hipError_t e = launch_fields(fp, (float*)ws, F, s);
     if (e != hipSuccess) return hip_fail(e, "field kernels");
     return P2S_OK;
@@ -388,6 +399,210 @@ SimLayout sim_layout(int C, int H, int W, int nz, int K, const Params& pr) {
     return L;
 }
 
+// ---------------------------------------------------------------- batches
+// Workspace of a batch: the device plan (frame table, then the per-stage item
+// prefix sums), then every frame's fields | field intermediate or weights |
+// blurred image, as in a single frame.
+struct BatchLayout {
+    size_t table, first, frames0, total;
+    std::vector<size_t> frame_off;
+};
+
+int batch_layout(const p2s_frame* fr, int n, int nz, int K, const Params& pr, BatchLayout* L) {
+    L->table = 0;
+    L->first = align256((size_t)n * sizeof(FrameDesc));
+    L->frames0 = L->first + align256((size_t)ST_N * (n + 1) * sizeof(int));
+    L->frame_off.resize(n);
+    size_t off = L->frames0;
+    for (int i = 0; i < n; ++i) {
+        int rc = check_frame(fr[i].C, fr[i].H, fr[i].W);
+        if (rc) return fail(rc, "frame %d: %s", i, g_err.c_str());
+        L->frame_off[i] = off;
+        off += sim_layout(fr[i].C, fr[i].H, fr[i].W, nz, K, pr).total;
+    }
+    L->total = n ? off : 0;
+    return P2S_OK;
+}
+
+struct BatchHost {
+    int n = 0;
+    p2s_precision prec = P2S_FP32;
+    double scale = 0.0;
+    const Basis* basis = nullptr;
+    const Mlp* mlp = nullptr;
+    void* pinned = nullptr;         // host copy of the device plan
+    size_t plan_bytes = 0;
+    void* plan_dev = nullptr;       // start of the workspace
+    hipEvent_t uploaded = nullptr;  // recorded after the last upload
+    bool upload_pending = false;
+    BatchLaunch bl{};
+};
+
+void batch_free(BatchHost* h) {
+    if (h->uploaded) {
+        if (h->upload_pending) (void)hipEventSynchronize(h->uploaded);
+        (void)hipEventDestroy(h->uploaded);
+    }
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    delete h;
+}
+
+int batch_create(const p2s_frame* frames, int n, int nz, const Basis& B, const Mlp& M, p2s_precision prec,
+                 const Params& pr, const p2s_batch_options* opt, void* ws, size_t ws_bytes, BatchHost** out) {
+    if (n < 0) return fail(P2S_EINVAL, "n must be >= 0, got %d", n);
+    if (n > 0 && !frames) return fail(P2S_EINVAL, "frames is NULL");
+    int rc = check_prec(prec);
+    if (rc) return rc;
+    if (nz < 3 || nz > P2S_MAX_ZERNIKE) return fail(P2S_EINVAL, "n_zernike must be in [3, %d], got %d", P2S_MAX_ZERNIKE, nz);
+    if (M.dims[0] != nz - 2)
+        return fail(P2S_EINVAL, "n_zernike - 2 = %d does not match the network input width %d", nz - 2, M.dims[0]);
+    if (M.dims[M.L] != B.K)
+        return fail(P2S_EINVAL, "network output width %d does not match the basis size K = %d", M.dims[M.L], B.K);
+    if (prec == P2S_BF16 && !B.bf16_ok)
+        return fail(P2S_EUNSUPPORTED, "BF16 blur needs a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", B.P);
+    const size_t wbytes = prec == P2S_FP32 ? M.bytes32 : M.bytes16;
+    if (wbytes > kMlpLdsBytes)
+        return fail(P2S_EUNSUPPORTED, "packed network weights (%zu bytes) exceed the %zu-byte LDS of one workgroup "
+                    "in this precision", wbytes, kMlpLdsBytes);
+    int rows = 16, persistent = 1;
+    if (opt) {
+        if (opt->blur_tile_rows != 16 && opt->blur_tile_rows != 8)
+            return fail(P2S_EINVAL, "blur_tile_rows must be 16 or 8, got %d", opt->blur_tile_rows);
+        if (opt->persistent != 0 && opt->persistent != 1)
+            return fail(P2S_EINVAL, "persistent must be 0 or 1, got %d", opt->persistent);
+        rows = opt->blur_tile_rows;
+        persistent = opt->persistent;
+    }
+    rows = blur_tile_rows(B.nmb, rows);
+    BatchLayout L;
+    rc = batch_layout(frames, n, nz, B.K, pr, &L);
+    if (rc) return rc;
+    if (n > 0 && !ws) return fail(P2S_EINVAL, "workspace is NULL");
+    if (ws_bytes < L.total) return fail(P2S_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    // Per-frame checks and descriptors.
+    std::vector<FrameDesc> desc(n);
+    std::vector<int> first((size_t)ST_N * (n + 1), 0);
+    std::vector<std::pair<const char*, const char*>> outs(n);
+    size_t lds_cols = 0, lds_rows = 0;
+    long long tot[ST_N] = {0, 0, 0, 0, 0};
+    char* base = (char*)ws;
+    for (int i = 0; i < n; ++i) {
+        const p2s_frame& f = frames[i];
+        FieldPlan fp;
+        rc = build_field_plan(f.H, f.W, f.D_over_r0, nz, f.seed, pr, &fp);
+        if (rc) return fail(rc, "frame %d: %s", i, g_err.c_str());
+        if (!f.image || !f.out) return fail(P2S_EINVAL, "frame %d: image or out is NULL", i);
+        const size_t HW = (size_t)f.H * f.W, nb = (size_t)f.C * HW * 4;
+        if (overlap(ws, L.total, f.image, nb) || overlap(ws, L.total, f.out, nb))
+            return fail(P2S_EINVAL, "frame %d: workspace overlaps image or out", i);
+        outs[i] = {(const char*)f.out, (const char*)f.out + nb};
+        const SimLayout S = sim_layout(f.C, f.H, f.W, nz, B.K, pr);
+        FrameDesc& d = desc[i];
+        d.image = f.image;
+        d.out = f.out;
+        char* fb = base + L.frame_off[i];
+        d.fields = (float*)(fb + S.fields);
+        d.w = (float*)(fb + S.region2);
+        d.blurred = (float*)(fb + S.blurred);
+        d.V = (float2*)(fb + S.region2);
+        d.twx = d.V + (size_t)fp.npairs * f.H * fp.Mx;
+        d.C = f.C;
+        d.H = f.H;
+        d.W = f.W;
+        d.tiles_x = (f.W + 31) / 32;
+        d.tiles_y = (f.H + rows - 1) / rows;
+        d.lg_cpb = fields_pick_lg(fp.Nfy, kColsLdsBudget, true);
+        d.lg_rpb = fields_pick_lg(fp.Nfx, kRowsLdsBudget, false);
+        d.ncol_chunks = (fp.Mx + (1 << d.lg_cpb) - 1) >> d.lg_cpb;
+        d.nrow_chunks = (f.H + (1 << d.lg_rpb) - 1) >> d.lg_rpb;
+        d.mlp_groups = (int)((HW + mlp_pixels_per_group() - 1) / mlp_pixels_per_group());
+        d.warp_tiles_x = (f.W + 63) / 64;
+        d.warp_tiles = d.warp_tiles_x * ((f.H + 3) / 4);
+        d.fp = fp;
+        lds_cols = std::max(lds_cols, fields_cols_lds(fp.Nfy, 1 << d.lg_cpb));
+        lds_rows = std::max(lds_rows, fields_rows_lds(fp.Nfx, 1 << d.lg_rpb));
+        const long long items[ST_N] = {(long long)fp.npairs * d.ncol_chunks, (long long)fp.npairs * d.nrow_chunks,
+                                       d.mlp_groups, (long long)f.C * d.tiles_x * d.tiles_y, d.warp_tiles};
+        for (int st = 0; st < ST_N; ++st) {
+            tot[st] += items[st];
+            if (tot[st] > std::numeric_limits<int>::max()) return fail(P2S_EINVAL, "batch too large");
+            first[(size_t)st * (n + 1) + i + 1] = (int)tot[st];
+        }
+    }
+    std::sort(outs.begin(), outs.end());
+    for (int i = 1; i < n; ++i)
+        if (outs[i].first < outs[i - 1].second) return fail(P2S_EINVAL, "output buffers of two frames overlap");
+    if (lds_cols > kMlpLdsBytes || lds_rows > kMlpLdsBytes)
+        return fail(P2S_EUNSUPPORTED, "field transforms need %zu / %zu bytes of LDS", lds_cols, lds_rows);
+    auto* h = new (std::nothrow) BatchHost();
+    if (!h) return fail(P2S_ENOMEM, "host allocation failed");
+    h->n = n;
+    h->prec = prec;
+    h->scale = 2.0 * (double)pr.q / M_PI;
+    h->basis = &B;
+    h->mlp = &M;
+    h->plan_bytes = L.frames0;
+    h->plan_dev = ws;
+    BatchLaunch& bl = h->bl;
+    bl.frames = (const FrameDesc*)(base + L.table);
+    bl.first = (const int*)(base + L.first);
+    bl.n = n;
+    bl.blur_rows = rows;
+    bl.lds[ST_COLS] = lds_cols;
+    bl.lds[ST_ROWS] = lds_rows;
+    for (int st = 0; st < ST_N; ++st) bl.items[st] = (int)tot[st];
+    if (n > 0) {
+        const int res[ST_N] = {fields_batch_resident(true, lds_cols), fields_batch_resident(false, lds_rows),
+                               mlp_batch_resident(M, prec), blur_batch_resident(B, prec, rows), warp_batch_resident()};
+        for (int st = 0; st < ST_N; ++st) bl.grid[st] = persistent ? std::min(bl.items[st], res[st]) : bl.items[st];
+        hipError_t e = hipHostMalloc(&h->pinned, h->plan_bytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            h->pinned = nullptr;
+            batch_free(h);
+            return fail(P2S_ENOMEM, "pinned plan buffer: %s", hipGetErrorString(e));
+        }
+        std::memset(h->pinned, 0, h->plan_bytes);
+        std::memcpy((char*)h->pinned + L.table, desc.data(), (size_t)n * sizeof(FrameDesc));
+        std::memcpy((char*)h->pinned + L.first, first.data(), first.size() * sizeof(int));
+        e = hipEventCreateWithFlags(&h->uploaded, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            h->uploaded = nullptr;
+            batch_free(h);
+            return hip_fail(e, "event");
+        }
+    }
+    *out = h;
+    return P2S_OK;
+}
+
+int batch_upload(BatchHost* h, hipStream_t s) {
+    if (h->n == 0) return P2S_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return hip_fail(e, "stream query");
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(P2S_EUNSUPPORTED, "upload the plan outside stream capture; capture p2s_batch_launch only");
+    e = hipMemcpyAsync(h->plan_dev, h->pinned, h->plan_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "plan upload");
+    e = hipEventRecord(h->uploaded, s);
+    if (e != hipSuccess) return hip_fail(e, "event record");
+    h->upload_pending = true;
+    return P2S_OK;
+}
+
+int batch_launch(const BatchHost* h, hipStream_t s) {
+    if (h->n == 0) return P2S_OK;
+    hipError_t e = launch_fields_batch(h->bl, s);
+    if (e != hipSuccess) return hip_fail(e, "batched field kernels");
+    e = launch_mlp_batch(*h->mlp, h->bl, h->prec, s);
+    if (e != hipSuccess) return hip_fail(e, "batched network kernel");
+    e = launch_blur_batch(*h->basis, h->bl, h->prec, s);
+    if (e != hipSuccess) return hip_fail(e, "batched blur kernel");
+    e = launch_warp_batch(h->bl, h->scale, s);
+    if (e != hipSuccess) return hip_fail(e, "batched warp kernel");
+    return P2S_OK;
+}
+
 }  // namespace
 
 uint16_t f32_to_bf16_rne(float x) {
@@ -398,6 +613,10 @@ uint16_t f32_to_bf16_rne(float x) {
 }
 
 }  // namespace p2s
+
+struct p2s_batch_s {
+    p2s::BatchHost* h;
+};
 
 using namespace p2s;
 
@@ -602,6 +821,87 @@ int p2s_simulate(const float* image, int C, int H, int W, double D_over_r0, int 
     if (rc) return rc;
     rc = warp_impl(bl, C, H, W, F, pr, out, s);
     if (rc) return rc;
+    return ok();
+}
+
+size_t p2s_batch_workspace_bytes(const p2s_frame* frames, int n, int n_zernike, int K, const p2s_params* params) {
+    Params pr;
+    if (read_params(params, &pr) || n < 0 || (n > 0 && !frames) || n_zernike < 1 || n_zernike > P2S_MAX_ZERNIKE ||
+        K < 1 || K > P2S_MAX_K)
+        return 0;
+    BatchLayout L;
+    const std::string saved = g_err;
+    if (batch_layout(frames, n, n_zernike, K, pr, &L)) {
+        g_err = saved;
+        return 0;
+    }
+    return L.total;
+}
+
+int p2s_batch_create(const p2s_frame* frames, int n, int n_zernike, p2s_basis_t basis, p2s_mlp_t mlp,
+                     p2s_precision precision, const p2s_params* params, const p2s_batch_options* options, void* ws,
+                     size_t ws_bytes, p2s_batch_t* out) {
+    try {
+        if (!out) return fail(P2S_EINVAL, "out is NULL");
+        if (!basis || !mlp) return fail(P2S_EINVAL, "basis or mlp is NULL");
+        Params pr;
+        int rc = read_params(params, &pr);
+        if (rc) return rc;
+        auto* hb = new (std::nothrow) p2s_batch_s();
+        if (!hb) return fail(P2S_ENOMEM, "host allocation failed");
+        rc = batch_create(frames, n, n_zernike, basis->b, mlp->m, precision, pr, options, ws, ws_bytes, &hb->h);
+        if (rc) {
+            delete hb;
+            return rc;
+        }
+        *out = hb;
+        return ok();
+    } catch (...) {
+        return fail(P2S_ENOMEM, "host allocation failed");
+    }
+}
+
+int p2s_batch_upload(p2s_batch_t batch, void* stream) {
+    if (!batch) return fail(P2S_EINVAL, "batch is NULL");
+    int rc = batch_upload(batch->h, (hipStream_t)stream);
+    return rc ? rc : ok();
+}
+
+int p2s_batch_launch(p2s_batch_t batch, void* stream) {
+    if (!batch) return fail(P2S_EINVAL, "batch is NULL");
+    int rc = batch_launch(batch->h, (hipStream_t)stream);
+    return rc ? rc : ok();
+}
+
+int p2s_batch_info(p2s_batch_t batch, int* items, int* grid) {
+    if (!batch) return fail(P2S_EINVAL, "batch is NULL");
+    for (int st = 0; st < ST_N; ++st) {
+        if (items) items[st] = batch->h->bl.items[st];
+        if (grid) grid[st] = batch->h->bl.grid[st];
+    }
+    return ok();
+}
+
+int p2s_batch_destroy(p2s_batch_t batch) {
+    if (!batch) return ok();
+    batch_free(batch->h);
+    delete batch;
+    return ok();
+}
+
+int p2s_simulate_batch(const p2s_frame* frames, int n, int n_zernike, p2s_basis_t basis, p2s_mlp_t mlp,
+                       p2s_precision precision, const p2s_params* params, void* ws, size_t ws_bytes, void* stream) {
+    p2s_batch_t b = nullptr;
+    int rc = p2s_batch_create(frames, n, n_zernike, basis, mlp, precision, params, nullptr, ws, ws_bytes, &b);
+    if (rc) return rc;
+    rc = batch_upload(b->h, (hipStream_t)stream);
+    if (!rc) rc = batch_launch(b->h, (hipStream_t)stream);
+    const std::string err = g_err;
+    p2s_batch_destroy(b);   // waits until the plan upload has been consumed
+    if (rc) {
+        g_err = err;
+        return rc;
+    }
     return ok();
 }
 

@@ -116,18 +116,16 @@ __device__ __forceinline__ void stage_window(float* __restrict__ dst, int ld, co
 // LDS tile of the image with a halo of R on every side (replicate border),
 // pitch padded by one float.  Tap u = 4 t + L/16 in row-major (dy, dx) order.
 template <int NMB, int NBLK>
-__global__ void __launch_bounds__(256) blur_f32_kernel(const float* __restrict__ img, int C, int H, int W, int P,
-                                                       const float* __restrict__ bp, int t4, int K,
-                                                       const float* __restrict__ w, float* __restrict__ out,
-                                                       int tiles_x) {
+__device__ __forceinline__ void blur_f32_tile(const float* __restrict__ img, int H, int W, int P, const float* __restrict__ bp,
+                              int t4, int K, const float* __restrict__ w, float* __restrict__ out, int tiles_x,
+                              int tile, int c) {
     constexpr int TY = NBLK * 2;                  // rows per workgroup: 4 waves x (NBLK/2) rows
     constexpr int LW = kTX + 2 * kMaxR;
     constexpr int PITCH = LW + 1;
     constexpr int LH = TY + 2 * kMaxR;
-    __shared__ float tile[LH * PITCH];
+    __shared__ float tile_lds[LH * PITCH];
     const int R = (P - 1) / 2;
-    const int c = blockIdx.y;                     // channel
-    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x0 = tx * kTX, y0 = ty * TY;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, m = lane & 15;
@@ -138,7 +136,8 @@ __global__ void __launch_bounds__(256) blur_f32_kernel(const float* __restrict__
 
     {
         const float* ic = img + c * HW;
-        stage_window<12>(tile, PITCH, ic, H, W, y0 - R, x0 - R, th, twd);
+        __syncthreads();                          // previous item of a persistent workgroup done with LDS
+        stage_window<12>(tile_lds, PITCH, ic, H, W, y0 - R, x0 - R, th, twd);
         __syncthreads();
         floatx4 acc[NBLK][NMB];
 #pragma unroll
@@ -155,7 +154,7 @@ __global__ void __launch_bounds__(256) blur_f32_kernel(const float* __restrict__
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb) av[mb] = bp[((size_t)t * NMB + mb) * 64 + lane];
 #pragma unroll
-            for (int b = 0; b < NBLK; ++b) pv[b] = tile[base + (b >> 1) * PITCH + (b & 1) * 16 + off];
+            for (int b = 0; b < NBLK; ++b) pv[b] = tile_lds[base + (b >> 1) * PITCH + (b & 1) * 16 + off];
             dx += 4;
             while (dx > R) {
                 dx -= P;
@@ -191,10 +190,8 @@ __global__ void __launch_bounds__(256) blur_f32_kernel(const float* __restrict__
 // and column chunk q at ColPk[ly + 8 q][lx].  Both share one pitch so that
 // the per-block address delta is the same constant for either kind.
 template <int P, int NMB, int NBLK>
-__global__ void __launch_bounds__(256) blur_bf16_kernel(const float* __restrict__ img, int C, int H, int W,
-                                                        const uint4* __restrict__ bp, int K,
-                                                        const float* __restrict__ w, float* __restrict__ out,
-                                                        int tiles_x) {
+__device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, int H, int W, const uint4* __restrict__ bp, int K,
+                               const float* __restrict__ w, float* __restrict__ out, int tiles_x, int tile, int c) {
     constexpr int R = (P - 1) / 2;
     constexpr int A8 = P / 8;                    // row chunks per PSF row
     constexpr int NROW = P * A8;
@@ -212,8 +209,7 @@ __global__ void __launch_bounds__(256) blur_bf16_kernel(const float* __restrict_
     __shared__ uint4 colpk[NR * PITCH];
     __shared__ float stage[SH * SW];
 
-    const int c = blockIdx.y;                     // channel
-    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x0 = tx * kTX, y0 = ty * TY;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, m = lane & 15;
@@ -223,6 +219,7 @@ __global__ void __launch_bounds__(256) blur_bf16_kernel(const float* __restrict_
 
     {
         const float* ic = img + c * HW;
+        __syncthreads();                          // previous item of a persistent workgroup done with LDS
         stage_window<14>(stage, SW, ic, H, W, y0 - R, x0 - R, SH, SW);
         __syncthreads();
         for (int idx = threadIdx.x; idx < PH * PITCH; idx += blockDim.x) {
@@ -293,13 +290,58 @@ __global__ void __launch_bounds__(256) blur_bf16_kernel(const float* __restrict_
     }
 }
 
+template <int NMB, int NBLK>
+__global__ void __launch_bounds__(256) blur_f32_kernel(const float* __restrict__ img, int H, int W, int P,
+                                                       const float* __restrict__ bp, int t4, int K,
+                                                       const float* __restrict__ w, float* __restrict__ out,
+                                                       int tiles_x) {
+    blur_f32_tile<NMB, NBLK>(img, H, W, P, bp, t4, K, w, out, tiles_x, blockIdx.x, blockIdx.y);
+}
+
+template <int P, int NMB, int NBLK>
+__global__ void __launch_bounds__(256) blur_bf16_kernel(const float* __restrict__ img, int H, int W,
+                                                        const uint4* __restrict__ bp, int K,
+                                                        const float* __restrict__ w, float* __restrict__ out,
+                                                        int tiles_x) {
+    blur_bf16_tile<P, NMB, NBLK>(img, H, W, bp, K, w, out, tiles_x, blockIdx.x, blockIdx.y);
+}
+
+// Batched, persistent forms over the (frame, channel, tile) list.
+template <int NMB, int NBLK>
+__global__ void __launch_bounds__(256) blur_f32_batch(const FrameDesc* __restrict__ fr, const int* __restrict__ first,
+                                                      int n, int P, const float* __restrict__ bp, int t4, int K) {
+    const int total = first[n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int f = find_frame(first, n, item);
+        const FrameDesc& d = fr[f];
+        const int l = item - first[f];
+        const int nt = d.tiles_x * d.tiles_y;
+        const int c = l / nt;
+        blur_f32_tile<NMB, NBLK>(d.image, d.H, d.W, P, bp, t4, K, d.w, d.blurred, d.tiles_x, l - c * nt, c);
+    }
+}
+
+template <int P, int NMB, int NBLK>
+__global__ void __launch_bounds__(256) blur_bf16_batch(const FrameDesc* __restrict__ fr, const int* __restrict__ first,
+                                                       int n, const uint4* __restrict__ bp, int K) {
+    const int total = first[n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int f = find_frame(first, n, item);
+        const FrameDesc& d = fr[f];
+        const int l = item - first[f];
+        const int nt = d.tiles_x * d.tiles_y;
+        const int c = l / nt;
+        blur_bf16_tile<P, NMB, NBLK>(d.image, d.H, d.W, bp, K, d.w, d.blurred, d.tiles_x, l - c * nt, c);
+    }
+}
+
 template <int NMB>
 hipError_t launch_f32(const Basis& b, const float* img, int C, int H, int W, const float* w, float* out,
                       hipStream_t s) {
     constexpr int NBLK = NMB <= 7 ? 8 : 4;
     constexpr int TY = NBLK * 2;
     const int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + TY - 1) / TY;
-    hipLaunchKernelGGL((blur_f32_kernel<NMB, NBLK>), dim3(tiles_x * tiles_y, C), dim3(256), 0, s, img, C, H, W, b.P,
+    hipLaunchKernelGGL((blur_f32_kernel<NMB, NBLK>), dim3(tiles_x * tiles_y, C), dim3(256), 0, s, img, H, W, b.P,
                        b.f32, b.t4, b.K, w, out, tiles_x);
     return hipGetLastError();
 }
@@ -310,7 +352,7 @@ hipError_t launch_bf16(const Basis& b, const float* img, int C, int H, int W, co
     constexpr int NBLK = NMB <= 7 ? 8 : 4;
     constexpr int TY = NBLK * 2;
     const int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + TY - 1) / TY;
-    hipLaunchKernelGGL((blur_bf16_kernel<P, NMB, NBLK>), dim3(tiles_x * tiles_y, C), dim3(256), 0, s, img, C, H, W,
+    hipLaunchKernelGGL((blur_bf16_kernel<P, NMB, NBLK>), dim3(tiles_x * tiles_y, C), dim3(256), 0, s, img, H, W,
                        reinterpret_cast<const uint4*>(b.bf16), b.K, w, out, tiles_x);
     return hipGetLastError();
 }
@@ -331,7 +373,88 @@ hipError_t dispatch_bf16(const Basis& b, const float* img, int C, int H, int W, 
     }
 }
 
+// Batched kernel instance for a basis, precision and tile height (nullptr if
+// there is none).  16-row tiles (8 pixel blocks per wave) need NMB <= 7.
+template <int NMB>
+const void* f32_batch_fn(int rows) {
+    if constexpr (NMB <= 7) {
+        if (rows == 16) return (const void*)blur_f32_batch<NMB, 8>;
+    }
+    return (const void*)blur_f32_batch<NMB, 4>;
+}
+
+template <int P, int NMB>
+const void* bf16_batch_fn(int rows) {
+    if constexpr (NMB <= 7) {
+        if (rows == 16) return (const void*)blur_bf16_batch<P, NMB, 8>;
+    }
+    return (const void*)blur_bf16_batch<P, NMB, 4>;
+}
+
+template <int P>
+const void* bf16_batch_fn_p(int nmb, int rows) {
+    switch (nmb) {
+        case 1: return bf16_batch_fn<P, 1>(rows);
+        case 2: return bf16_batch_fn<P, 2>(rows);
+        case 3: return bf16_batch_fn<P, 3>(rows);
+        case 4: return bf16_batch_fn<P, 4>(rows);
+        case 5: return bf16_batch_fn<P, 5>(rows);
+        case 6: return bf16_batch_fn<P, 6>(rows);
+        case 7: return bf16_batch_fn<P, 7>(rows);
+        case 8: return bf16_batch_fn<P, 8>(rows);
+        default: return nullptr;
+    }
+}
+
+const void* blur_batch_fn(const Basis& b, p2s_precision prec, int rows) {
+    if (prec == P2S_FP32) {
+        switch (b.nmb) {
+            case 1: return f32_batch_fn<1>(rows);
+            case 2: return f32_batch_fn<2>(rows);
+            case 3: return f32_batch_fn<3>(rows);
+            case 4: return f32_batch_fn<4>(rows);
+            case 5: return f32_batch_fn<5>(rows);
+            case 6: return f32_batch_fn<6>(rows);
+            case 7: return f32_batch_fn<7>(rows);
+            case 8: return f32_batch_fn<8>(rows);
+            default: return nullptr;
+        }
+    }
+    if (!b.bf16_ok) return nullptr;
+    switch (b.P) {
+        case 9: return bf16_batch_fn_p<9>(b.nmb, rows);
+        case 17: return bf16_batch_fn_p<17>(b.nmb, rows);
+        case 25: return bf16_batch_fn_p<25>(b.nmb, rows);
+        case 33: return bf16_batch_fn_p<33>(b.nmb, rows);
+        default: return nullptr;
+    }
+}
+
 }  // namespace
+
+int blur_tile_rows(int nmb, int preferred) { return (nmb <= 7 && preferred == 16) ? 16 : 8; }
+
+int blur_batch_resident(const Basis& b, p2s_precision prec, int rows) {
+    const void* fn = blur_batch_fn(b, prec, blur_tile_rows(b.nmb, rows));
+    return fn ? resident_workgroups(fn, 256, 0) : 0;
+}
+
+hipError_t launch_blur_batch(const Basis& b, const BatchLaunch& bl, p2s_precision prec, hipStream_t s) {
+    if (bl.items[ST_BLUR] == 0) return hipSuccess;
+    const void* fn = blur_batch_fn(b, prec, bl.blur_rows);
+    if (!fn) return hipErrorInvalidValue;
+    const FrameDesc* fr = bl.frames;
+    const int* first = bl.first + ST_BLUR * (bl.n + 1);
+    int n = bl.n, P = b.P, t4 = b.t4, K = b.K;
+    const float* bp32 = b.f32;
+    const uint4* bp16 = reinterpret_cast<const uint4*>(b.bf16);
+    if (prec == P2S_FP32) {
+        void* args[] = {&fr, &first, &n, &P, &bp32, &t4, &K};
+        return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(256), args, 0, s);
+    }
+    void* args[] = {&fr, &first, &n, &bp16, &K};
+    return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(256), args, 0, s);
+}
 
 hipError_t launch_blur(const Basis& b, const float* img, int C, int H, int W, const float* w, p2s_precision prec,
                        float* out, hipStream_t s) {

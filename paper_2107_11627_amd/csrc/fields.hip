@@ -188,19 +188,18 @@ __device__ __forceinline__ float gauss_filter(int k, int N, float corr_len) {
 
 __device__ __forceinline__ int ld_of(int N) { return N | 1; }   // odd stride spreads LDS banks
 
-// Kernel 1: noise spectrum of band columns -> inverse FFT along y.
-__global__ void __launch_bounds__(kThreads) fields_cols_kernel(FieldPlan fp, float2* __restrict__ V, int lg_cpb,
-                                                               float2* __restrict__ twx_out) {
-    extern __shared__ float2 smem[];
+// Column work item: plane pair q, band columns j0 .. j0 + 2^lg_cpb - 1.  Noise
+// spectrum of those columns -> inverse FFT along y -> V.  Item (q=0, j0=0)
+// also publishes the row transforms' twiddle table.
+__device__ __forceinline__ void fields_cols_item(const FieldPlan& fp, float2* __restrict__ V, float2* __restrict__ twx_out,
+                                 int lg_cpb, int q, int j0, float2* smem) {
     const int cpb = 1 << lg_cpb;
     const int N = fp.Nfy, ld = ld_of(N);
     float2* buf0 = smem;
     float2* buf1 = smem + cpb * ld;
     float2* tw = smem + 2 * cpb * ld;
     float* filt = reinterpret_cast<float*>(tw + N);
-    const int q = blockIdx.y;
-    const int j0 = blockIdx.x * cpb;
-    if (blockIdx.x == 0 && blockIdx.y == 0) {   // the row kernel's twiddles, evaluated once
+    if (q == 0 && j0 == 0) {
         for (int k = threadIdx.x; k < fp.Nfx; k += blockDim.x) {
             double sn, cs;
             sincospi(-2.0 * (double)k / (double)fp.Nfx, &sn, &cs);
@@ -234,20 +233,18 @@ __global__ void __launch_bounds__(kThreads) fields_cols_kernel(FieldPlan fp, flo
         const int j = j0 + c;
         if (j < Mx) Vq[(size_t)y * Mx + j] = X[c * ld + y];
     }
+    __syncthreads();                           // LDS free for the next item
 }
 
-// Kernel 2: band spectrum of output rows -> inverse FFT along x -> two planes.
-__global__ void __launch_bounds__(kThreads) fields_rows_kernel(FieldPlan fp, const float2* __restrict__ V,
-                                                               float* __restrict__ F, int lg_rpb,
-                                                               const float2* __restrict__ twx) {
-    extern __shared__ float2 smem[];
+// Row work item: plane pair q, output rows y0 .. y0 + 2^lg_rpb - 1.  V scattered
+// into the band bins -> inverse FFT along x -> planes 2q, 2q+1.
+__device__ __forceinline__ void fields_rows_item(const FieldPlan& fp, const float2* __restrict__ V, float* __restrict__ F,
+                                 const float2* __restrict__ twx, int lg_rpb, int q, int y0, float2* smem) {
     const int rpb = 1 << lg_rpb;
     const int N = fp.Nfx, ld = ld_of(N);
     float2* buf0 = smem;
     float2* buf1 = smem + rpb * ld;
     float2* tw = smem + 2 * rpb * ld;
-    const int q = blockIdx.y;
-    const int y0 = blockIdx.x * rpb;
     const int H = fp.H, W = fp.W, Mx = fp.Mx;
     for (int k = threadIdx.x; k < N; k += blockDim.x) tw[k] = twx[k];
     for (int idx = threadIdx.x; idx < rpb * ld; idx += blockDim.x) buf0[idx] = make_float2(0.f, 0.f);
@@ -276,6 +273,47 @@ __global__ void __launch_bounds__(kThreads) fields_rows_kernel(FieldPlan fp, con
             if (has1) F1[(size_t)y * W + x] = s1 * v.y;
         }
     }
+    __syncthreads();                           // LDS free for the next item
+}
+
+__global__ void __launch_bounds__(kThreads) fields_cols_kernel(FieldPlan fp, float2* __restrict__ V, int lg_cpb,
+                                                               float2* __restrict__ twx_out) {
+    extern __shared__ float2 smem[];
+    fields_cols_item(fp, V, twx_out, lg_cpb, blockIdx.y, blockIdx.x << lg_cpb, smem);
+}
+
+__global__ void __launch_bounds__(kThreads) fields_rows_kernel(FieldPlan fp, const float2* __restrict__ V,
+                                                               float* __restrict__ F, int lg_rpb,
+                                                               const float2* __restrict__ twx) {
+    extern __shared__ float2 smem[];
+    fields_rows_item(fp, V, F, twx, lg_rpb, blockIdx.y, blockIdx.x << lg_rpb, smem);
+}
+
+// Batched, persistent forms: workgroups stride over the (frame, item) list.
+__global__ void __launch_bounds__(kThreads) fields_cols_batch(const FrameDesc* __restrict__ fr,
+                                                              const int* __restrict__ first, int n) {
+    extern __shared__ float2 smem[];
+    const int total = first[n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int f = find_frame(first, n, item);
+        const FrameDesc& d = fr[f];
+        const int l = item - first[f];
+        const int q = l / d.ncol_chunks;
+        fields_cols_item(d.fp, d.V, d.twx, d.lg_cpb, q, (l - q * d.ncol_chunks) << d.lg_cpb, smem);
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) fields_rows_batch(const FrameDesc* __restrict__ fr,
+                                                              const int* __restrict__ first, int n) {
+    extern __shared__ float2 smem[];
+    const int total = first[n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int f = find_frame(first, n, item);
+        const FrameDesc& d = fr[f];
+        const int l = item - first[f];
+        const int q = l / d.nrow_chunks;
+        fields_rows_item(d.fp, d.V, d.fields, d.twx, d.lg_rpb, q, (l - q * d.nrow_chunks) << d.lg_rpb, smem);
+    }
 }
 
 __global__ void debug_noise_kernel(int Nfy, int Nfx, int pair, uint32_t k0, uint32_t k1, uint32_t* raw,
@@ -293,16 +331,43 @@ __global__ void debug_noise_kernel(int Nfy, int Nfx, int pair, uint32_t k0, uint
     }
 }
 
-size_t cols_lds(int N, int nb) { return (size_t)(2 * nb * (N | 1) + N) * 8 + (size_t)N * 4; }
-size_t rows_lds(int N, int nb) { return (size_t)(2 * nb * (N | 1) + N) * 8; }
+}  // namespace
 
-int pick_lg(int N, size_t budget, size_t (*lds)(int, int)) {
+size_t fields_cols_lds(int N, int nb) { return (size_t)(2 * nb * (N | 1) + N) * 8 + (size_t)N * 4; }
+size_t fields_rows_lds(int N, int nb) { return (size_t)(2 * nb * (N | 1) + N) * 8; }
+
+int fields_pick_lg(int N, size_t budget, bool cols) {
     int lg = 3;
-    while (lg > 0 && lds(N, 1 << lg) > budget) --lg;
+    while (lg > 0 && (cols ? fields_cols_lds(N, 1 << lg) : fields_rows_lds(N, 1 << lg)) > budget) --lg;
     return lg;
 }
 
-}  // namespace
+int fields_batch_resident(bool cols, size_t lds) {
+    return resident_workgroups(cols ? (const void*)fields_cols_batch : (const void*)fields_rows_batch, kThreads, lds);
+}
+
+hipError_t launch_fields_batch(const BatchLaunch& bl, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)fields_cols_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute((const void*)fields_rows_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (bl.items[ST_COLS] > 0) {
+        hipLaunchKernelGGL(fields_cols_batch, dim3(bl.grid[ST_COLS]), dim3(kThreads), bl.lds[ST_COLS], s, bl.frames,
+                           bl.first + ST_COLS * (bl.n + 1), bl.n);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (bl.items[ST_ROWS] > 0)
+        hipLaunchKernelGGL(fields_rows_batch, dim3(bl.grid[ST_ROWS]), dim3(kThreads), bl.lds[ST_ROWS], s, bl.frames,
+                           bl.first + ST_ROWS * (bl.n + 1), bl.n);
+    return hipGetLastError();
+}
 
 int factor_radices(int n, int* rad) {
     int k = 0;
@@ -315,9 +380,9 @@ int factor_radices(int n, int* rad) {
 
 hipError_t launch_fields(const FieldPlan& fp, float* V, float* F, hipStream_t s) {
     const size_t kMaxLds = 160 * 1024;
-    const int lc = pick_lg(fp.Nfy, 96 * 1024, cols_lds);
-    const int lr = pick_lg(fp.Nfx, 48 * 1024, rows_lds);
-    const size_t bc = cols_lds(fp.Nfy, 1 << lc), br = rows_lds(fp.Nfx, 1 << lr);
+    const int lc = fields_pick_lg(fp.Nfy, kColsLdsBudget, true);
+    const int lr = fields_pick_lg(fp.Nfx, kRowsLdsBudget, false);
+    const size_t bc = fields_cols_lds(fp.Nfy, 1 << lc), br = fields_rows_lds(fp.Nfx, 1 << lr);
     if (bc > kMaxLds || br > kMaxLds) return hipErrorInvalidValue;
     static bool attr = false;
     if (!attr) {

@@ -74,6 +74,75 @@ struct FieldPlan {
     float sigma[P2S_MAX_ZERNIKE];    // per-plane standard deviation
 };
 
+// ------------------------------------------------------------- batches
+// One frame of a batch as the batched kernels see it (device memory).
+struct FrameDesc {
+    const float* image;
+    float* out;
+    float* fields;                   // [nz][H][W]
+    float* w;                        // [H*W][K]
+    float* blurred;                  // [C][H][W]
+    float2* V;                       // field intermediate [pairs][H][Mx]
+    float2* twx;                     // [Nfx] row twiddles
+    int C, H, W;
+    int tiles_x, tiles_y;            // blur tiles
+    int lg_cpb, lg_rpb;              // field transforms per workgroup item (log2)
+    int ncol_chunks, nrow_chunks;    // field items per plane pair
+    int mlp_groups;                  // network pixel groups
+    int warp_tiles_x, warp_tiles;    // warp items
+    FieldPlan fp;
+};
+
+enum { ST_COLS = 0, ST_ROWS, ST_MLP, ST_BLUR, ST_WARP, ST_N };
+
+// Launch description of a planned batch: device pointers to the frame table
+// and to the per-stage prefix sums of work items (first[stage][n + 1]), plus
+// per-stage grid and LDS sizes.
+struct BatchLaunch {
+    const FrameDesc* frames;
+    const int* first;
+    int n;
+    int items[ST_N];
+    int grid[ST_N];
+    size_t lds[ST_N];
+    int blur_rows;                   // 16 or 8 rows per blur tile
+};
+
+// Index of the frame whose items contain `item` (first[0] = 0, first[n] = total).
+__device__ __forceinline__ int find_frame(const int* __restrict__ first, int n, int item) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first[mid] <= item) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+constexpr size_t kColsLdsBudget = 96 * 1024;
+constexpr size_t kRowsLdsBudget = 48 * 1024;
+size_t fields_cols_lds(int N, int nb);
+size_t fields_rows_lds(int N, int nb);
+int fields_pick_lg(int N, size_t budget, bool cols);
+hipError_t launch_fields_batch(const BatchLaunch& bl, hipStream_t s);
+hipError_t launch_mlp_batch(const Mlp& m, const BatchLaunch& bl, p2s_precision prec, hipStream_t s);
+hipError_t launch_blur_batch(const Basis& b, const BatchLaunch& bl, p2s_precision prec, hipStream_t s);
+hipError_t launch_warp_batch(const BatchLaunch& bl, double scale, hipStream_t s);
+int mlp_pixels_per_group();
+int blur_tile_rows(int nmb, int preferred);
+// Workgroups of each batched kernel the whole device holds at once.
+int fields_batch_resident(bool cols, size_t lds);
+int mlp_batch_resident(const Mlp& m, p2s_precision prec);
+int blur_batch_resident(const Basis& b, p2s_precision prec, int rows);
+int warp_batch_resident();
+
+int num_cus();
+inline int resident_workgroups(const void* fn, int threads, size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, lds) != hipSuccess || nb < 1) nb = 1;
+    return nb * num_cus();
+}
+
 int factor_radices(int n, int* rad);   // -> number of passes, 0 if not 5-smooth
 hipError_t launch_fields(const FieldPlan& fp, float* V, float* F, hipStream_t s);
 hipError_t launch_debug_noise(int Nfy, int Nfx, int pair, uint32_t k0, uint32_t k1,

@@ -101,6 +101,66 @@ __device__ __forceinline__ void store_w(const float (&act)[kNb][MB][4], float* _
 }
 
 // ------------------------------------------------------------------ FP32
+// One group of kPixPerGroup pixels starting at pixel grp * kPixPerGroup of a
+// frame with HW pixels; `fields` points at plane 2 (alpha_4) of the frame.
+template <int MB>
+__device__ __forceinline__ void mlp_f32_group(const MlpArgs& a, const float* __restrict__ lds_w, const float* __restrict__ bias,
+                              const float* __restrict__ fields, float* __restrict__ wout, int HW, int grp) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, m = lane & 15;
+    const int pix0 = grp * kPixPerGroup + wave * kNb * 16;
+    int pixc[kNb];
+#pragma unroll
+    for (int nb = 0; nb < kNb; ++nb) pixc[nb] = min(pix0 + nb * 16 + m, HW - 1);
+    float act[kNb][MB][4];
+    floatx4 acc[kNb][MB];
+#pragma unroll
+    for (int nb = 0; nb < kNb; ++nb)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[nb][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // layer 0: B operand straight from the field planes (feature 4 kc + g)
+    const float* w0 = lds_w + a.woff[0];
+    for (int kc = 0; kc < a.nkc0; ++kc) {
+        const int f = min(4 * kc + g, a.n_in - 1);
+        const float fmask = (4 * kc + g < a.n_in) ? 1.0f : 0.0f;
+        float x[kNb];
+#pragma unroll
+        for (int nb = 0; nb < kNb; ++nb) x[nb] = fields[(size_t)f * HW + pixc[nb]] * fmask;
+        float wa[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) wa[mb] = w0[(mb * a.nkc0 + kc) * 64 + lane];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < kNb; ++nb)
+                acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[mb], x[nb], acc[nb][mb], 0, 0, 0);
+    }
+    finish_layer<MB>(acc, act, bias + a.boff[0], g, a.L == 1);
+    for (int l = 1; l < a.L; ++l) {
+        const float* wl = lds_w + a.woff[l];
+        constexpr int NKC = 4 * MB;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            float wa[NKC];
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) wa[kc] = wl[(mb * NKC + kc) * 64 + lane];
+            floatx4 c[kNb];
+#pragma unroll
+            for (int nb = 0; nb < kNb; ++nb) c[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+                for (int nb = 0; nb < kNb; ++nb)
+                    c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[kc], act[nb][kc >> 2][kc & 3], c[nb], 0, 0, 0);
+#pragma unroll
+            for (int nb = 0; nb < kNb; ++nb) acc[nb][mb] = c[nb];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        finish_layer<MB>(acc, act, bias + a.boff[l], g, l == a.L - 1);
+    }
+    store_w<MB>(act, wout, pix0, m, g, HW, a.K);
+}
+
 template <int MB>
 __global__ void __launch_bounds__(kWaves * 64) mlp_f32_kernel(MlpArgs a, const float* __restrict__ fields,
                                                               const float* __restrict__ wg,
@@ -109,60 +169,23 @@ __global__ void __launch_bounds__(kWaves * 64) mlp_f32_kernel(MlpArgs a, const f
     extern __shared__ float lds_w[];
     stage_weights(lds_w, wg, a.wtotal);
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 4, m = lane & 15;
-    for (int grp = blockIdx.x; grp < a.ngroups; grp += gridDim.x) {
-        const int pix0 = grp * kPixPerGroup + wave * kNb * 16;
-        int pixc[kNb];
-#pragma unroll
-        for (int nb = 0; nb < kNb; ++nb) pixc[nb] = min(pix0 + nb * 16 + m, a.HW - 1);
-        float act[kNb][MB][4];
-        floatx4 acc[kNb][MB];
-#pragma unroll
-        for (int nb = 0; nb < kNb; ++nb)
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[nb][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
-        // layer 0: B operand straight from the field planes (feature 4 kc + g)
-        const float* w0 = lds_w + a.woff[0];
-        for (int kc = 0; kc < a.nkc0; ++kc) {
-            const int f = min(4 * kc + g, a.n_in - 1);
-            const float fmask = (4 * kc + g < a.n_in) ? 1.0f : 0.0f;
-            float x[kNb];
-#pragma unroll
-            for (int nb = 0; nb < kNb; ++nb) x[nb] = fields[(size_t)f * a.HW + pixc[nb]] * fmask;
-            float wa[MB];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) wa[mb] = w0[(mb * a.nkc0 + kc) * 64 + lane];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < kNb; ++nb)
-                    acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[mb], x[nb], acc[nb][mb], 0, 0, 0);
-        }
-        finish_layer<MB>(acc, act, bias + a.boff[0], g, a.L == 1);
-        for (int l = 1; l < a.L; ++l) {
-            const float* wl = lds_w + a.woff[l];
-            constexpr int NKC = 4 * MB;
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                float wa[NKC];
-#pragma unroll
-                for (int kc = 0; kc < NKC; ++kc) wa[kc] = wl[(mb * NKC + kc) * 64 + lane];
-                floatx4 c[kNb];
-#pragma unroll
-                for (int nb = 0; nb < kNb; ++nb) c[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kc = 0; kc < NKC; ++kc)
-#pragma unroll
-                    for (int nb = 0; nb < kNb; ++nb)
-                        c[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[kc], act[nb][kc >> 2][kc & 3], c[nb], 0, 0, 0);
-#pragma unroll
-                for (int nb = 0; nb < kNb; ++nb) acc[nb][mb] = c[nb];
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            finish_layer<MB>(acc, act, bias + a.boff[l], g, l == a.L - 1);
-        }
-        store_w<MB>(act, wout, pix0, m, g, a.HW, a.K);
+    for (int grp = blockIdx.x; grp < a.ngroups; grp += gridDim.x)
+        mlp_f32_group<MB>(a, lds_w, bias, fields, wout, a.HW, grp);
+}
+
+template <int MB>
+__global__ void __launch_bounds__(kWaves * 64) mlp_f32_batch(MlpArgs a, const FrameDesc* __restrict__ fr,
+                                                             const int* __restrict__ first, int n,
+                                                             const float* __restrict__ wg,
+                                                             const float* __restrict__ bias) {
+    extern __shared__ float lds_w[];
+    stage_weights(lds_w, wg, a.wtotal);
+    __syncthreads();
+    const int total = first[n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int f = find_frame(first, n, item);
+        const int HW = fr[f].H * fr[f].W;
+        mlp_f32_group<MB>(a, lds_w, bias, fr[f].fields + 2 * (size_t)HW, fr[f].w, HW, item - first[f]);
     }
 }
 
@@ -181,6 +204,134 @@ __device__ __forceinline__ void split8(const float v[8], bf16x8& hi, bf16x8& lo)
 }
 
 template <int MB>
+__device__ __forceinline__ void mlp_bf16_group(const MlpArgs& a, const uint4* __restrict__ lds_w16, const float* __restrict__ bias,
+                               const float* __restrict__ fields, float* __restrict__ wout, int HW, int grp) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, m = lane & 15;
+    constexpr int MBE = (MB + 1) & ~1;      // even block count: chunks pair blocks
+    constexpr int NKC = MBE / 2;
+    const int pix0 = grp * kPixPerGroup + wave * kNb * 16;
+    int pixc[kNb];
+#pragma unroll
+    for (int nb = 0; nb < kNb; ++nb) pixc[nb] = min(pix0 + nb * 16 + m, HW - 1);
+    float act[kNb][MBE][4];
+    floatx4 acc[kNb][MB];
+    // layer 0: chunk kc covers features 32 kc + 8 g + e
+    {
+        bf16x8 xh[kNb][2], xl[kNb][2];
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) {
+            float v[kNb][8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int f = 32 * kc + 8 * g + e;
+                const int fc = min(f, a.n_in - 1);
+                const float fm = f < a.n_in ? 1.0f : 0.0f;
+#pragma unroll
+                for (int nb = 0; nb < kNb; ++nb) v[nb][e] = fields[(size_t)fc * HW + pixc[nb]] * fm;
+            }
+#pragma unroll
+            for (int nb = 0; nb < kNb; ++nb) split8(v[nb], xh[nb][kc], xl[nb][kc]);
+        }
+        const uint4* w0 = lds_w16 + a.woff[0];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            bf16x8 wa[2];
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc) wa[kc] = __builtin_bit_cast(bf16x8, w0[(mb * 2 + kc) * 64 + lane]);
+            floatx4 c[kNb];
+#pragma unroll
+            for (int nb = 0; nb < kNb; ++nb) c[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc) {
+                if (kc < a.nkc0) {
+#pragma unroll
+                    for (int nb = 0; nb < kNb; ++nb) {
+                        c[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kc], xh[nb][kc], c[nb], 0, 0, 0);
+                        c[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kc], xl[nb][kc], c[nb], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int nb = 0; nb < kNb; ++nb) acc[nb][mb] = c[nb];
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < kNb; ++nb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) act[nb][MBE - 1][i] = 0.0f;   // padding block when MB is odd
+    {
+        // bias/ReLU into act[.][0..MB)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float b = bias[a.boff[0] + 16 * mb + 4 * g + i];
+#pragma unroll
+                for (int nb = 0; nb < kNb; ++nb) {
+                    const float v = acc[nb][mb][i] + b;
+                    act[nb][mb][i] = (a.L == 1) ? v : fmaxf(v, 0.0f);
+                }
+            }
+    }
+    for (int l = 1; l < a.L; ++l) {
+        bf16x8 xh[kNb][NKC], xl[kNb][NKC];
+#pragma unroll
+        for (int nb = 0; nb < kNb; ++nb)
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) {
+                float v[8];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    v[e] = act[nb][2 * kc][e];
+                    v[4 + e] = act[nb][2 * kc + 1][e];
+                }
+                split8(v, xh[nb][kc], xl[nb][kc]);
+            }
+        const uint4* wl = lds_w16 + a.woff[l];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            bf16x8 wa[NKC];
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) wa[kc] = __builtin_bit_cast(bf16x8, wl[(mb * NKC + kc) * 64 + lane]);
+            floatx4 c[kNb];
+#pragma unroll
+            for (int nb = 0; nb < kNb; ++nb) c[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+                for (int nb = 0; nb < kNb; ++nb) {
+                    c[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kc], xh[nb][kc], c[nb], 0, 0, 0);
+                    c[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kc], xl[nb][kc], c[nb], 0, 0, 0);
+                }
+#pragma unroll
+            for (int nb = 0; nb < kNb; ++nb) acc[nb][mb] = c[nb];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const bool last = (l == a.L - 1);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float b = bias[a.boff[l] + 16 * mb + 4 * g + i];
+#pragma unroll
+                for (int nb = 0; nb < kNb; ++nb) {
+                    const float v = acc[nb][mb][i] + b;
+                    act[nb][mb][i] = last ? v : fmaxf(v, 0.0f);
+                }
+            }
+    }
+    float outv[kNb][MB][4];
+#pragma unroll
+    for (int nb = 0; nb < kNb; ++nb)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) outv[nb][mb][i] = act[nb][mb][i];
+    store_w<MB>(outv, wout, pix0, m, g, HW, a.K);
+}
+
+template <int MB>
 __global__ void __launch_bounds__(kWaves * 64) mlp_bf16_kernel(MlpArgs a, const float* __restrict__ fields,
                                                                const uint4* __restrict__ wg,
                                                                const float* __restrict__ bias,
@@ -188,157 +339,76 @@ __global__ void __launch_bounds__(kWaves * 64) mlp_bf16_kernel(MlpArgs a, const 
     extern __shared__ uint4 lds_w16[];
     stage_weights(lds_w16, wg, a.wtotal);
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 4, m = lane & 15;
-    constexpr int MBE = (MB + 1) & ~1;      // even block count: chunks pair blocks
-    constexpr int NKC = MBE / 2;
-    for (int grp = blockIdx.x; grp < a.ngroups; grp += gridDim.x) {
-        const int pix0 = grp * kPixPerGroup + wave * kNb * 16;
-        int pixc[kNb];
-#pragma unroll
-        for (int nb = 0; nb < kNb; ++nb) pixc[nb] = min(pix0 + nb * 16 + m, a.HW - 1);
-        float act[kNb][MBE][4];
-        floatx4 acc[kNb][MB];
-        // layer 0: chunk kc covers features 32 kc + 8 g + e
-        {
-            bf16x8 xh[kNb][2], xl[kNb][2];
-#pragma unroll
-            for (int kc = 0; kc < 2; ++kc) {
-                float v[kNb][8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int f = 32 * kc + 8 * g + e;
-                    const int fc = min(f, a.n_in - 1);
-                    const float fm = f < a.n_in ? 1.0f : 0.0f;
-#pragma unroll
-                    for (int nb = 0; nb < kNb; ++nb) v[nb][e] = fields[(size_t)fc * a.HW + pixc[nb]] * fm;
-                }
-#pragma unroll
-                for (int nb = 0; nb < kNb; ++nb) split8(v[nb], xh[nb][kc], xl[nb][kc]);
-            }
-            const uint4* w0 = lds_w16 + a.woff[0];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                bf16x8 wa[2];
-#pragma unroll
-                for (int kc = 0; kc < 2; ++kc) wa[kc] = __builtin_bit_cast(bf16x8, w0[(mb * 2 + kc) * 64 + lane]);
-                floatx4 c[kNb];
-#pragma unroll
-                for (int nb = 0; nb < kNb; ++nb) c[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kc = 0; kc < 2; ++kc) {
-                    if (kc < a.nkc0) {
-#pragma unroll
-                        for (int nb = 0; nb < kNb; ++nb) {
-                            c[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kc], xh[nb][kc], c[nb], 0, 0, 0);
-                            c[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kc], xl[nb][kc], c[nb], 0, 0, 0);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int nb = 0; nb < kNb; ++nb) acc[nb][mb] = c[nb];
-            }
-        }
-#pragma unroll
-        for (int nb = 0; nb < kNb; ++nb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) act[nb][MBE - 1][i] = 0.0f;   // padding block when MB is odd
-        {
-            // bias/ReLU into act[.][0..MB)
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float b = bias[a.boff[0] + 16 * mb + 4 * g + i];
-#pragma unroll
-                    for (int nb = 0; nb < kNb; ++nb) {
-                        const float v = acc[nb][mb][i] + b;
-                        act[nb][mb][i] = (a.L == 1) ? v : fmaxf(v, 0.0f);
-                    }
-                }
-        }
-        for (int l = 1; l < a.L; ++l) {
-            bf16x8 xh[kNb][NKC], xl[kNb][NKC];
-#pragma unroll
-            for (int nb = 0; nb < kNb; ++nb)
-#pragma unroll
-                for (int kc = 0; kc < NKC; ++kc) {
-                    float v[8];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        v[e] = act[nb][2 * kc][e];
-                        v[4 + e] = act[nb][2 * kc + 1][e];
-                    }
-                    split8(v, xh[nb][kc], xl[nb][kc]);
-                }
-            const uint4* wl = lds_w16 + a.woff[l];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                bf16x8 wa[NKC];
-#pragma unroll
-                for (int kc = 0; kc < NKC; ++kc) wa[kc] = __builtin_bit_cast(bf16x8, wl[(mb * NKC + kc) * 64 + lane]);
-                floatx4 c[kNb];
-#pragma unroll
-                for (int nb = 0; nb < kNb; ++nb) c[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kc = 0; kc < NKC; ++kc)
-#pragma unroll
-                    for (int nb = 0; nb < kNb; ++nb) {
-                        c[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kc], xh[nb][kc], c[nb], 0, 0, 0);
-                        c[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kc], xl[nb][kc], c[nb], 0, 0, 0);
-                    }
-#pragma unroll
-                for (int nb = 0; nb < kNb; ++nb) acc[nb][mb] = c[nb];
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            const bool last = (l == a.L - 1);
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float b = bias[a.boff[l] + 16 * mb + 4 * g + i];
-#pragma unroll
-                    for (int nb = 0; nb < kNb; ++nb) {
-                        const float v = acc[nb][mb][i] + b;
-                        act[nb][mb][i] = last ? v : fmaxf(v, 0.0f);
-                    }
-                }
-        }
-        float outv[kNb][MB][4];
-#pragma unroll
-        for (int nb = 0; nb < kNb; ++nb)
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) outv[nb][mb][i] = act[nb][mb][i];
-        store_w<MB>(outv, wout, pix0, m, g, a.HW, a.K);
+    for (int grp = blockIdx.x; grp < a.ngroups; grp += gridDim.x)
+        mlp_bf16_group<MB>(a, lds_w16, bias, fields, wout, a.HW, grp);
+}
+
+template <int MB>
+__global__ void __launch_bounds__(kWaves * 64) mlp_bf16_batch(MlpArgs a, const FrameDesc* __restrict__ fr,
+                                                              const int* __restrict__ first, int n,
+                                                              const uint4* __restrict__ wg,
+                                                              const float* __restrict__ bias) {
+    extern __shared__ uint4 lds_w16[];
+    stage_weights(lds_w16, wg, a.wtotal);
+    __syncthreads();
+    const int total = first[n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int f = find_frame(first, n, item);
+        const int HW = fr[f].H * fr[f].W;
+        mlp_bf16_group<MB>(a, lds_w16, bias, fr[f].fields + 2 * (size_t)HW, fr[f].w, HW, item - first[f]);
     }
 }
 
-int num_cus() {
-    static int n = 0;
-    if (n == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
-            n = 256;
+
+template <int MB>
+hipError_t set_attrs() {
+    static bool attr = false;
+    if (!attr) {
+        const void* ks[] = {(const void*)mlp_f32_kernel<MB>, (const void*)mlp_bf16_kernel<MB>,
+                            (const void*)mlp_f32_batch<MB>, (const void*)mlp_bf16_batch<MB>};
+        for (const void* k : ks) {
+            hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+        }
+        attr = true;
     }
-    return n;
+    return hipSuccess;
+}
+
+void fill_weight_args(const Mlp& mm, p2s_precision prec, MlpArgs& a) {
+    if (prec == P2S_FP32) {
+        for (int l = 0; l < mm.L; ++l) a.woff[l] = (int)(mm.off32[l] / sizeof(float));
+        a.nkc0 = mm.nkc32[0];
+        a.wtotal = (int)(mm.bytes32 / sizeof(float));
+    } else {
+        for (int l = 0; l < mm.L; ++l) a.woff[l] = (int)(mm.off16[l] / 16);
+        a.nkc0 = mm.nkc16[0];
+        a.wtotal = (int)(mm.bytes16 / 16);
+    }
+}
+
+template <int MB>
+hipError_t launch_mb_batch(const Mlp& mm, const MlpArgs& a0, const BatchLaunch& bl, p2s_precision prec,
+                           hipStream_t s) {
+    hipError_t e = set_attrs<MB>();
+    if (e != hipSuccess) return e;
+    MlpArgs a = a0;
+    fill_weight_args(mm, prec, a);
+    const int* first = bl.first + ST_MLP * (bl.n + 1);
+    if (prec == P2S_FP32)
+        hipLaunchKernelGGL(mlp_f32_batch<MB>, dim3(bl.grid[ST_MLP]), dim3(kWaves * 64), mm.bytes32, s, a, bl.frames,
+                           first, bl.n, mm.w32, mm.bias);
+    else
+        hipLaunchKernelGGL(mlp_bf16_batch<MB>, dim3(bl.grid[ST_MLP]), dim3(kWaves * 64), mm.bytes16, s, a, bl.frames,
+                           first, bl.n, reinterpret_cast<const uint4*>(mm.w16), mm.bias);
+    return hipGetLastError();
 }
 
 template <int MB>
 hipError_t launch_mb(const Mlp& mm, const MlpArgs& a0, const float* fields, p2s_precision prec, float* w,
                      hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)mlp_f32_kernel<MB>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void*)mlp_bf16_kernel<MB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    hipError_t e0 = set_attrs<MB>();
+    if (e0 != hipSuccess) return e0;
     MlpArgs a = a0;
     const int grid = std::min(a.ngroups, num_cus() * 2);
     if (prec == P2S_FP32) {
@@ -358,6 +428,45 @@ hipError_t launch_mb(const Mlp& mm, const MlpArgs& a0, const float* fields, p2s_
 }
 
 }  // namespace
+
+int num_cus() {
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+    }
+    return n;
+}
+
+int mlp_pixels_per_group() { return kPixPerGroup; }
+
+int mlp_batch_resident(const Mlp& mm, p2s_precision prec) {
+    (void)mm;
+    (void)prec;
+    return 2 * num_cus();   // weights staged once per workgroup; LDS allows at most two
+}
+
+hipError_t launch_mlp_batch(const Mlp& mm, const BatchLaunch& bl, p2s_precision prec, hipStream_t s) {
+    if (bl.items[ST_MLP] == 0) return hipSuccess;
+    MlpArgs a{};
+    a.L = mm.L;
+    a.n_in = mm.dims[0];
+    a.K = mm.dims[mm.L];
+    for (int l = 0; l < mm.L; ++l) a.boff[l] = mm.boff[l];
+    switch (mm.mb) {
+        case 1: return launch_mb_batch<1>(mm, a, bl, prec, s);
+        case 2: return launch_mb_batch<2>(mm, a, bl, prec, s);
+        case 3: return launch_mb_batch<3>(mm, a, bl, prec, s);
+        case 4: return launch_mb_batch<4>(mm, a, bl, prec, s);
+        case 5: return launch_mb_batch<5>(mm, a, bl, prec, s);
+        case 6: return launch_mb_batch<6>(mm, a, bl, prec, s);
+        case 7: return launch_mb_batch<7>(mm, a, bl, prec, s);
+        case 8: return launch_mb_batch<8>(mm, a, bl, prec, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_mlp(const Mlp& mm, const float* fields, int H, int W, p2s_precision prec, float* w,
                       hipStream_t s) {

@@ -11,11 +11,12 @@
 namespace p2s {
 namespace {
 
-__global__ void __launch_bounds__(256) warp_kernel(const float* __restrict__ in, int C, int H, int W,
-                                                   const float* __restrict__ tilt, double scale,
-                                                   float* __restrict__ out) {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+// One 64 x 4 pixel block of one frame.
+__device__ __forceinline__ void warp_block(const float* __restrict__ in, int C, int H, int W,
+                                           const float* __restrict__ tilt, double scale, float* __restrict__ out,
+                                           int bx, int by) {
+    const int x = bx * 64 + (threadIdx.x & 63);
+    const int y = by * 4 + (threadIdx.x >> 6);
     if (x >= W || y >= H) return;
     const size_t HW = (size_t)H * W;
     const size_t i = (size_t)y * W + x;
@@ -35,7 +36,35 @@ __global__ void __launch_bounds__(256) warp_kernel(const float* __restrict__ in,
     }
 }
 
+__global__ void __launch_bounds__(256) warp_kernel(const float* __restrict__ in, int C, int H, int W,
+                                                   const float* __restrict__ tilt, double scale,
+                                                   float* __restrict__ out) {
+    warp_block(in, C, H, W, tilt, scale, out, blockIdx.x, blockIdx.y);
+}
+
+// Batched, persistent form over the (frame, 64 x 4 block) list.
+__global__ void __launch_bounds__(256) warp_batch(const FrameDesc* __restrict__ fr, const int* __restrict__ first,
+                                                  int n, double scale) {
+    const int total = first[n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int f = find_frame(first, n, item);
+        const FrameDesc& d = fr[f];
+        const int l = item - first[f];
+        const int by = l / d.warp_tiles_x;
+        warp_block(d.blurred, d.C, d.H, d.W, d.fields, scale, d.out, l - by * d.warp_tiles_x, by);
+    }
+}
+
 }  // namespace
+
+int warp_batch_resident() { return resident_workgroups((const void*)warp_batch, 256, 0); }
+
+hipError_t launch_warp_batch(const BatchLaunch& bl, double scale, hipStream_t s) {
+    if (bl.items[ST_WARP] == 0) return hipSuccess;
+    hipLaunchKernelGGL(warp_batch, dim3(bl.grid[ST_WARP]), dim3(256), 0, s, bl.frames,
+                       bl.first + ST_WARP * (bl.n + 1), bl.n, scale);
+    return hipGetLastError();
+}
 
 hipError_t launch_warp(const float* in, int C, int H, int W, const float* tilt, double scale, float* out,
                        hipStream_t s) {

@@ -26,7 +26,8 @@ EXPORTS = [
     "p2s_fields_workspace_bytes", "p2s_workspace_bytes", "p2s_basis_create",
     "p2s_basis_destroy", "p2s_basis_info", "p2s_mlp_create", "p2s_mlp_destroy",
     "p2s_mlp_info", "p2s_make_fields", "p2s_mlp", "p2s_blur", "p2s_warp",
-    "p2s_simulate", "p2s_debug_noise",
+    "p2s_simulate", "p2s_debug_noise", "p2s_batch_workspace_bytes", "p2s_batch_create",
+    "p2s_batch_upload", "p2s_batch_launch", "p2s_batch_info", "p2s_batch_destroy", "p2s_simulate_batch",
 ]
 
 
@@ -38,6 +39,19 @@ class P2SError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [("corr_len_px", C.c_float), ("q_sampling", C.c_float)]
+
+
+class Frame(C.Structure):
+    """One frame of a batch (device pointers)."""
+    _fields_ = [("image", C.c_void_p), ("out", C.c_void_p), ("C", C.c_int), ("H", C.c_int), ("W", C.c_int),
+                ("D_over_r0", C.c_double), ("seed", C.c_uint64)]
+
+
+class BatchOptions(C.Structure):
+    _fields_ = [("blur_tile_rows", C.c_int), ("persistent", C.c_int)]
+
+
+N_BATCH_STAGES = 5   # column and row field transforms, network, blur, warp
 
 
 _lib = None
@@ -71,8 +85,18 @@ def lib():
         L.p2s_warp.argtypes = [vp, i, i, i, vp, vp, vp, vp]
         L.p2s_simulate.argtypes = [vp, i, i, i, d, i, vp, vp, u64, i, vp, vp, vp, sz, vp]
         L.p2s_debug_noise.argtypes = [i, i, i, u64, vp, vp, vp]
+        L.p2s_batch_workspace_bytes.argtypes = [vp, i, i, i, vp]
+        L.p2s_batch_workspace_bytes.restype = sz
+        L.p2s_batch_create.argtypes = [vp, i, i, vp, vp, i, vp, vp, vp, sz, C.POINTER(vp)]
+        L.p2s_batch_upload.argtypes = [vp, vp]
+        L.p2s_batch_launch.argtypes = [vp, vp]
+        L.p2s_batch_info.argtypes = [vp, C.POINTER(i), C.POINTER(i)]
+        L.p2s_batch_destroy.argtypes = [vp]
+        L.p2s_simulate_batch.argtypes = [vp, i, i, vp, vp, i, vp, vp, sz, vp]
+        sized = ("p2s_version", "p2s_last_error", "p2s_fields_workspace_bytes", "p2s_workspace_bytes",
+                 "p2s_batch_workspace_bytes")
         for name in EXPORTS:
-            if name not in ("p2s_version", "p2s_last_error", "p2s_fields_workspace_bytes", "p2s_workspace_bytes"):
+            if name not in sized:
                 getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -248,6 +272,85 @@ def debug_noise(Nfy, Nfx, pair, seed, raw, normals=None, stream=None):
                                  _stream(stream)))
 
 
+# --------------------------------------------------------------- batches
+def _frames(images, outs, d_over_r0s, seeds):
+    import torch
+    n = len(images)
+    if not (len(outs) == n and len(d_over_r0s) == n and len(seeds) == n):
+        raise ValueError("images, outs, d_over_r0s and seeds must have the same length")
+    arr = (Frame * max(n, 1))()
+    for k in range(n):
+        im, o = images[k], outs[k]
+        if im.dim() != 3:
+            raise ValueError(f"image {k} must be [C][H][W]")
+        C_, H, W = im.shape
+        arr[k] = Frame(_ptr(im, torch.float32, None, f"image {k}"), _ptr(o, torch.float32, (C_, H, W), f"out {k}"),
+                       C_, H, W, float(d_over_r0s[k]), int(seeds[k]) & (2 ** 64 - 1))
+    return arr, n
+
+
+def batch_workspace_bytes(shapes, n_zernike: int, K: int, corr_len_px: float = 16.0) -> int:
+    """Workspace bytes for frames of the given (C, H, W) shapes; 0 if invalid."""
+    n = len(shapes)
+    arr = (Frame * max(n, 1))()
+    for k, (C_, H, W) in enumerate(shapes):
+        arr[k] = Frame(None, None, C_, H, W, 0.0, 0)
+    return lib().p2s_batch_workspace_bytes(arr, n, n_zernike, K, _params(corr_len_px))
+
+
+class Batch:
+    """A planned batch: frames of any sizes through the batched kernels.
+
+    create (here) -> upload() -> launch() [graph-capturable, repeatable] -> close().
+    The tensors passed in are kept referenced for the handle's lifetime."""
+
+    def __init__(self, images, outs, d_over_r0s, seeds, basis: Basis, net: Mlp, precision, ws, n_zernike=35,
+                 corr_len_px=16.0, q_sampling=2.0, blur_tile_rows=16, persistent=True):
+        self.handle = None
+        arr, n = _frames(images, outs, d_over_r0s, seeds)
+        self._keep = (list(images), list(outs), basis, net, ws)
+        self.n = n
+        opt = BatchOptions(int(blur_tile_rows), 1 if persistent else 0)
+        h = C.c_void_p()
+        _check(lib().p2s_batch_create(arr, n, n_zernike, basis.handle, net.handle, _prec(precision),
+                                      _params(corr_len_px, q_sampling), C.byref(opt),
+                                      _ptr(ws, name="ws") if ws is not None else None,
+                                      ws.numel() * ws.element_size() if ws is not None else 0, C.byref(h)))
+        self.handle = h
+
+    def upload(self, stream=None):
+        _check(lib().p2s_batch_upload(self.handle, _stream(stream)))
+
+    def launch(self, stream=None):
+        _check(lib().p2s_batch_launch(self.handle, _stream(stream)))
+
+    def info(self):
+        items = (C.c_int * N_BATCH_STAGES)()
+        grid = (C.c_int * N_BATCH_STAGES)()
+        _check(lib().p2s_batch_info(self.handle, items, grid))
+        return list(items), list(grid)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().p2s_batch_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def simulate_batch(images, d_over_r0s, seeds, basis: Basis, net: Mlp, precision, outs, ws, n_zernike=35,
+                   corr_len_px=16.0, q_sampling=2.0, stream=None):
+    arr, n = _frames(images, outs, d_over_r0s, seeds)
+    _check(lib().p2s_simulate_batch(arr, n, n_zernike, basis.handle, net.handle, _prec(precision),
+                                    _params(corr_len_px, q_sampling),
+                                    _ptr(ws, name="ws") if ws is not None else None,
+                                    ws.numel() * ws.element_size() if ws is not None else 0, _stream(stream)))
+
+
 class Simulator:
     """Resident basis + network + workspace for repeated frames of one size."""
 
@@ -277,3 +380,31 @@ class Simulator:
         simulate(image, d_over_r0, self.basis, self.net, seed, precision, out, ws, self.n_zernike,
                  self.corr_len_px, self.q_sampling, stream)
         return out
+
+    def batch_workspace(self, shapes):
+        import torch
+        n = batch_workspace_bytes(shapes, self.n_zernike, self.basis.K, self.corr_len_px)
+        if n == 0 and len(shapes) > 0:
+            raise P2SError(P2S_EINVAL, "invalid frame sizes")
+        return torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+
+    def plan(self, images, d_over_r0s, seeds, precision="bf16", outs=None, ws=None, **options):
+        """A Batch over these frames (outputs allocated if not given)."""
+        import torch
+        if outs is None:
+            outs = [torch.empty_like(im) for im in images]
+        if ws is None:
+            ws = self.batch_workspace([tuple(im.shape) for im in images])
+        return Batch(images, outs, d_over_r0s, seeds, self.basis, self.net, precision, ws, self.n_zernike,
+                     self.corr_len_px, self.q_sampling, **options), outs
+
+    def batch(self, images, d_over_r0s, seeds, precision="bf16", outs=None, ws=None, stream=None):
+        """All frames through one batched launch per stage; returns the outputs."""
+        import torch
+        if outs is None:
+            outs = [torch.empty_like(im) for im in images]
+        if ws is None:
+            ws = self.batch_workspace([tuple(im.shape) for im in images])
+        simulate_batch(images, d_over_r0s, seeds, self.basis, self.net, precision, outs, ws, self.n_zernike,
+                       self.corr_len_px, self.q_sampling, stream)
+        return outs

@@ -69,6 +69,32 @@ def test_workspace_sizes(p2s):
     assert p2s.workspace_bytes(1, 512, 512, 35, 200) == 0
 
 
+def test_batch_workspace_sizes(p2s):
+    shapes = [(1, 512, 512), (3, 128, 100), (2, 1, 1)]
+    per = sum(p2s.workspace_bytes(c, h, w, 35, 100) for c, h, w in shapes)
+    got = p2s.batch_workspace_bytes(shapes, 35, 100)
+    plan = got - per                    # frame table + per-stage prefix sums, 256-byte pieces
+    assert 0 < plan and plan % 256 == 0 and plan <= 3 * 2048 + 256
+    assert p2s.batch_workspace_bytes([], 35, 100) == 0
+    assert p2s.batch_workspace_bytes([(5, 8, 8)], 35, 100) == 0
+    assert p2s.batch_workspace_bytes([(1, 8, 8)], 35, 200) == 0
+
+
+def test_batch_validation_without_device(p2s):
+    lib = p2s.lib()
+    vp = C.c_void_p
+    h = vp()
+    fr = (p2s.Frame * 1)(p2s.Frame(vp(0x1000), vp(0x2000), 1, 8, 8, 1.0, 0))
+    assert lib.p2s_batch_create(fr, 1, 35, None, None, 1, None, None, vp(0x9000), 1 << 30, C.byref(h)) == p2s.P2S_EINVAL
+    assert b"basis" in lib.p2s_last_error()
+    assert lib.p2s_batch_create(fr, 1, 35, vp(1), vp(1), 1, None, None, vp(0x9000), 1 << 30, None) == p2s.P2S_EINVAL
+    for name in ("p2s_batch_upload", "p2s_batch_launch"):
+        assert getattr(lib, name)(None, None) == p2s.P2S_EINVAL
+    assert lib.p2s_batch_info(None, None, None) == p2s.P2S_EINVAL
+    assert lib.p2s_batch_destroy(None) == p2s.P2S_OK
+    assert lib.p2s_simulate_batch(fr, 1, 35, None, None, 1, None, vp(0x9000), 1 << 30, None) == p2s.P2S_EINVAL
+
+
 def test_validation_without_device(p2s):
     """Every check below fails before any HIP call, so no GPU is needed."""
     lib = p2s.lib()
