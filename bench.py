@@ -112,6 +112,146 @@ def blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C):
                       "algorithmic_bytes_per_launch": 4 * (2 * C * H * W + H * W * K)}), flush=True)
 
 
+def batch_section(args, torch, p2s, S, pbasis):
+    """The two batch workloads (64 RGB 256x256 frames; 200 ragged frames) with
+    the shared K=100, P=33 basis: BF16 and FP32 through the batched kernels
+    (plan uploaded once, the launch captured in a HIP graph and replayed) and,
+    for comparison, the same frames one p2s_simulate call at a time."""
+    from paper_2107_11627_amd import autotune
+
+    wl0 = S.workload("batch256")
+    z, d = wl0.basis_draws()
+    basis, _ = pbasis.learn_basis(z, d, wl0.K, wl0.P, wl0.n_zernike)
+    Ws, bs = wl0.mlp()
+    sim = p2s.Simulator(basis, Ws, bs, n_zernike=wl0.n_zernike)
+    out = {}
+    for name in ("batch256", "ragged"):
+        wl = S.workload(name)
+        t0 = time.perf_counter()
+        imgs = [torch.from_numpy(f.image()).cuda() for f in wl.frames]
+        dd = [f.d_over_r0 for f in wl.frames]
+        seeds = [f.field_seed for f in wl.frames]
+        log(f"[bench] {name}: {len(imgs)} frames ready in {time.perf_counter() - t0:.1f} s")
+        shapes = [tuple(im.shape) for im in imgs]
+        mpix = sum(c * h * w for c, h, w in shapes) / 1e6
+        outs = [torch.empty_like(im) for im in imgs]
+        ws = sim.batch_workspace(shapes)
+        rec = {"frames": len(imgs), "megapixels_x_channels": mpix, "workspace_GiB": ws.numel() / 2 ** 30}
+        for prec in ("bf16", "fp32"):
+            opt = autotune.tune(sim, imgs, dd, seeds, prec, outs=outs, ws=ws)
+            b = p2s.Batch(imgs, outs, dd, seeds, sim.basis, sim.net, prec, ws, sim.n_zernike, **opt)
+            b.upload()
+            b.launch()
+            torch.cuda.synchronize()
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(s):
+                with torch.cuda.graph(g, stream=s):
+                    b.launch(stream=s)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            reps = args.batch_reps
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            items, grid = b.info()
+            # the same frames one at a time through p2s_simulate (one untimed pass
+            # first, so that the workspace has reached its largest size)
+            for k, im in enumerate(imgs):
+                sim(im, dd[k], seeds[k], prec, out=outs[k])
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for k, im in enumerate(imgs):
+                sim(im, dd[k], seeds[k], prec, out=outs[k])
+            e1.record()
+            torch.cuda.synchronize()
+            ms_solo = e0.elapsed_time(e1)
+            rec[prec] = {"batched_frames_per_s": len(imgs) / (ms / 1e3), "batch_ms": ms,
+                         "per_frame_frames_per_s": len(imgs) / (ms_solo / 1e3), "per_frame_ms": ms_solo,
+                         "schedule": opt, "tuner_us": autotune.last_timings(shapes, prec, sim.basis.K, sim.basis.P),
+                         "items": items, "grid": grid}
+            log(f"[bench] {name} {prec}: batched {rec[prec]['batched_frames_per_s']:.1f} frames/s "
+                f"({ms:.2f} ms/batch, {opt}), one at a time {rec[prec]['per_frame_frames_per_s']:.1f} frames/s")
+            del g
+            b.close()
+        rec["bf16_batched_vs_fp32_per_frame"] = (rec["bf16"]["batched_frames_per_s"] /
+                                                 rec["fp32"]["per_frame_frames_per_s"])
+        out[name] = rec
+        del imgs, outs, ws
+        torch.cuda.empty_cache()
+    return out
+
+
+def serving_section(args, torch, p2s, S, pbasis):
+    """The serving workload: requests of 128..2048 RGB arrive as a Poisson
+    process at a fixed rate; the continuous-batching loop runs them in BF16
+    under the HBM admission budget.  Also: the same requests all queued at
+    once (saturated throughput), and the plain FP32 per-frame path (one
+    p2s_simulate call per request, in arrival order)."""
+    from paper_2107_11627_amd import serving as sv
+
+    wl = S.workload("serving")
+    z, d = wl.basis_draws()
+    basis, _ = pbasis.learn_basis(z, d, wl.K, wl.P, wl.n_zernike)
+    Ws, bs = wl.mlp()
+    sim = p2s.Simulator(basis, Ws, bs, n_zernike=wl.n_zernike)
+    frames = wl.frames[: args.serving_requests]
+    t0 = time.perf_counter()
+    imgs = [S.blob_image_device(f.H, f.W, f.C, f.image_seed, f.noise_std, device_noise=True) for f in frames]
+    torch.cuda.synchronize()
+    log(f"[bench] serving: {len(imgs)} request images on the device in {time.perf_counter() - t0:.1f} s")
+    rate = wl.extra["arrival_rate_hz"]
+    budget = wl.extra["hbm_budget_bytes"]
+    arr = sv.poisson_arrivals(len(frames), rate, wl.extra["arrival_seed"])
+
+    def requests(arrivals):
+        return [sv.Request(i, imgs[i], f.d_over_r0, f.field_seed, float(arrivals[i])) for i, f in enumerate(frames)]
+
+    res = {"requests": len(frames), "arrival_rate_hz": rate, "budget_GiB": budget / 2 ** 30,
+           "megapixels_x_channels": sum(f.C * f.H * f.W for f in frames) / 1e6}
+    for label, arrivals in (("poisson", arr), ("saturated", np.zeros(len(frames)))):
+        ex = sv.GpuExecutor(sim, "bf16", budget, n_slots=args.serving_slots)
+        eng = sv.Engine(ex, budget, n_slots=args.serving_slots, max_batch_frames=args.serving_max_batch)
+        # warm the kernels and the plan path once on a few requests
+        sv.run(eng, requests(np.zeros(len(frames)))[:4])
+        eng = sv.Engine(ex, budget, n_slots=args.serving_slots, max_batch_frames=args.serving_max_batch)
+        st = sv.run(eng, requests(arrivals))
+        res[label] = st
+        log(f"[bench] serving {label}: {st['frames_per_s']:.1f} frames/s, p50 {st['latency_ms']['p50']:.2f} ms, "
+            f"p99 {st['latency_ms']['p99']:.2f} ms, {st['batches']} batches (mean {st['mean_batch_frames']:.1f} "
+            f"frames), peak {st['peak_hbm_bytes'] / 2 ** 30:.1f} GiB")
+        del ex, eng
+        torch.cuda.empty_cache()
+    # plain FP32 per-frame path over the same requests
+    lat = []
+    out = None
+    t = time.perf_counter()
+    for i, im in enumerate(imgs):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        out = sim(im, frames[i].d_over_r0, frames[i].field_seed, "fp32")
+        b.record()
+        lat.append((a, b))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    lt = np.array([a.elapsed_time(b) for a, b in lat])
+    res["fp32_per_frame"] = {"frames_per_s": len(imgs) / wall,
+                             "latency_ms": {"p50": float(np.percentile(lt, 50)), "p99": float(np.percentile(lt, 99))},
+                             "note": "device time per p2s_simulate call, frames back to back"}
+    res["bf16_serving_vs_fp32_per_frame"] = res["saturated"]["frames_per_s"] / res["fp32_per_frame"]["frames_per_s"]
+    log(f"[bench] serving fp32 per-frame: {res['fp32_per_frame']['frames_per_s']:.1f} frames/s")
+    del imgs, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +261,12 @@ def main():
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-batches", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--serving-slots", type=int, default=2)
+    ap.add_argument("--serving-max-batch", type=int, default=16)
     ap.add_argument("--mode", choices=["frame", "blur", "copy"], default="frame",
                     help="frame: the benchmark; blur: only the fused blur of the workload (for counter runs); "
                          "copy: a plain device copy of known size (calibrates byte counters)")
@@ -238,6 +384,9 @@ def main():
     fp32_roof = {"bound": "mfma", "achieved": flops / fp32_blur_s / 1e12, "peak": PEAK_FP32_TFLOPS,
                  "frac": flops / fp32_blur_s / 1e12 / PEAK_FP32_TFLOPS}
 
+    batches = None if args.no_batches else batch_section(args, torch, p2s, S, pbasis)
+    serving = None if args.no_serving else serving_section(args, torch, p2s, S, pbasis)
+
     cpu = None
     errs = None
     if not args.no_cpu_baseline:
@@ -283,6 +432,8 @@ def main():
                  "blur_roofline": fp32_roof},
         "stages_us": {"bf16": res["bf16"]["stages_us"], "fp32": res["fp32"]["stages_us"]},
         "roofline": roofline,
+        "batches": batches,
+        "serving": serving,
         "cpu_baseline": cpu,
         "rel_l2_vs_oracle": errs,
         "paper_context": "0.026 s/frame on a Tesla V100 for a 256x256 frame (Table 2); different hardware and frame",

@@ -14,7 +14,8 @@ in the design notes):
 * ``single512``  512x512 C=1, D/r0=3, K=100 basis of 33x33, MLP 33-100-100-100.
 * ``batch256``   64 frames 256x256 RGB, D/r0 ~ U[1,4].
 * ``ragged``     200 frames, sizes from a fixed set, C in {1,3}, D/r0 ~ U[0.5,5].
-* ``serving``    Poisson arrivals, sizes 128..2048 (multiples of 64), RGB.
+* ``serving``    1000 requests, Poisson arrivals at 250/s, sizes 128..2048
+                 (multiples of 64), RGB, admission budget 32 GiB.
 """
 from __future__ import annotations
 
@@ -25,7 +26,9 @@ import numpy as np
 
 __all__ = [
     "bf16_representable",
+    "blob_params",
     "blob_image",
+    "blob_image_device",
     "xavier_mlp",
     "standard_normals",
     "FrameSpec",
@@ -46,6 +49,23 @@ def bf16_representable(x: np.ndarray) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).reshape(a.shape)
 
 
+def blob_params(H: int, W: int, C: int, seed: int, n_blobs: int = 20,
+                sigma_range: Tuple[float, float] = (3.0, 12.0),
+                amp_range: Tuple[float, float] = (0.2, 1.0)):
+    """The random draws behind ``blob_image``: per channel the blob centres
+    (cy, cx), widths and amplitudes, then the generator positioned for the
+    optional noise."""
+    rng = np.random.default_rng(seed)
+    per_channel = []
+    for _ in range(C):
+        cy = rng.uniform(0.0, H, n_blobs)
+        cx = rng.uniform(0.0, W, n_blobs)
+        sg = rng.uniform(sigma_range[0], sigma_range[1], n_blobs)
+        am = rng.uniform(amp_range[0], amp_range[1], n_blobs)
+        per_channel.append((cy, cx, sg, am))
+    return per_channel, rng
+
+
 def blob_image(H: int, W: int, C: int, seed: int, n_blobs: int = 20,
                sigma_range: Tuple[float, float] = (3.0, 12.0),
                amp_range: Tuple[float, float] = (0.2, 1.0),
@@ -53,17 +73,13 @@ def blob_image(H: int, W: int, C: int, seed: int, n_blobs: int = 20,
     """Sum of ``n_blobs`` isotropic Gaussian blobs per channel, min-max
     normalised to [0, 1] per channel, plus optional zero-mean uniform noise of
     standard deviation ``noise_std`` (not clipped).  Returns float32 [C][H][W]."""
-    rng = np.random.default_rng(seed)
+    chans, rng = blob_params(H, W, C, seed, n_blobs, sigma_range, amp_range)
     yy = np.arange(H, dtype=np.float64)[:, None]
     xx = np.arange(W, dtype=np.float64)[None, :]
     out = np.empty((C, H, W), dtype=np.float64)
-    for c in range(C):
-        cy = rng.uniform(0.0, H, n_blobs)
-        cx = rng.uniform(0.0, W, n_blobs)
-        sg = rng.uniform(sigma_range[0], sigma_range[1], n_blobs)
-        am = rng.uniform(amp_range[0], amp_range[1], n_blobs)
+    for c, (cy, cx, sg, am) in enumerate(chans):
         img = np.zeros((H, W), dtype=np.float64)
-        for b in range(n_blobs):   # separable: exp(-(dy^2 + dx^2)/2s^2) = g(dy) g(dx)
+        for b in range(len(cy)):   # separable: exp(-(dy^2 + dx^2)/2s^2) = g(dy) g(dx)
             s2 = 2.0 * sg[b] ** 2
             img += (am[b] * np.exp(-(yy - cy[b]) ** 2 / s2)) * np.exp(-(xx - cx[b]) ** 2 / s2)
         lo, hi = img.min(), img.max()
@@ -72,6 +88,37 @@ def blob_image(H: int, W: int, C: int, seed: int, n_blobs: int = 20,
         a = noise_std * np.sqrt(3.0)
         out += rng.uniform(-a, a, size=out.shape)
     return out.astype(np.float32)
+
+
+def blob_image_device(H: int, W: int, C: int, seed: int, noise_std: float = 0.0, device="cuda",
+                      device_noise: bool = False):
+    """The same image as ``blob_image`` (same draws; the sums evaluated in
+    float64 by torch on ``device``, so equal up to rounding), for workloads too
+    large to build on the host.  The noise is drawn on the host as in
+    ``blob_image``, or with ``device_noise`` from torch's generator on the
+    device seeded with ``seed`` (a different but equally distributed draw)."""
+    import torch
+    chans, rng = blob_params(H, W, C, seed)
+    yy = torch.arange(H, dtype=torch.float64, device=device)[:, None]
+    xx = torch.arange(W, dtype=torch.float64, device=device)[None, :]
+    out = torch.empty((C, H, W), dtype=torch.float64, device=device)
+    for c, (cy, cx, sg, am) in enumerate(chans):
+        s2 = torch.from_numpy(2.0 * sg ** 2).to(device)
+        gy = torch.from_numpy(am).to(device)[:, None] * torch.exp(
+            -(yy.T - torch.from_numpy(cy).to(device)[:, None]) ** 2 / s2[:, None])          # [n][H]
+        gx = torch.exp(-(xx - torch.from_numpy(cx).to(device)[:, None]) ** 2 / s2[:, None])  # [n][W]
+        img = gy.T @ gx
+        lo, hi = img.min(), img.max()
+        out[c] = (img - lo) / (hi - lo) if bool(hi > lo) else torch.zeros_like(img)
+    if noise_std > 0.0:
+        a = noise_std * np.sqrt(3.0)
+        if device_noise:
+            g = torch.Generator(device=device)
+            g.manual_seed(int(seed))
+            out += (torch.rand((C, H, W), generator=g, dtype=torch.float64, device=device) * 2.0 - 1.0) * a
+        else:
+            out += torch.from_numpy(rng.uniform(-a, a, size=(C, H, W))).to(device)
+    return out.to(torch.float32)
 
 
 def xavier_mlp(dims: Sequence[int], seed: int, bias_scale: float = 0.0):
@@ -177,7 +224,8 @@ def workload(name: str) -> Workload:
         d = rng.uniform(0.5, 6.0, n)
         fr = [FrameSpec(int(hs[i]), int(ws[i]), 3, float(d[i]), 7000 + i, 3000 + i, 0.02)
               for i in range(n)]
-        return Workload(name, fr, extra={"arrival_seed": 41, "hbm_budget_bytes": 32 << 30}, **shared)
+        return Workload(name, fr, extra={"arrival_seed": 41, "arrival_rate_hz": 250.0,
+                                         "hbm_budget_bytes": 32 << 30}, **shared)
     raise KeyError(name)
 
 
