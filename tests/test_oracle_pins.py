@@ -391,3 +391,57 @@ def test_normals_moments():
     # neighbouring bins are uncorrelated
     zz = philox.complex_normal_bins(256, 256, 0, 7)
     assert abs(np.mean(zz.real[:, 0::2] * zz.real[:, 1::2])) < 4 / math.sqrt(zz.size / 2)
+
+
+# ------------------------------------------------------------------ FP8 E4M3
+def test_e4m3_rounding_matches_torch_cast():
+    """The oracle's E4M3 rounding against torch's float8_e4m3fn conversion (an
+    independent implementation of the same OCP format): random magnitudes
+    over the whole normal and subnormal range, and every midpoint between
+    neighbouring codes (ties go to the even code)."""
+    torch = pytest.importorskip("torch")
+    from oracle import fp8
+    rng = np.random.default_rng(8)
+    mag = np.ldexp(rng.uniform(1.0, 2.0, 200000), rng.integers(-14, 9, 200000))
+    x = (np.where(rng.random(200000) < 0.5, -1.0, 1.0) * np.minimum(mag, 448.0)).astype(np.float32)
+    codes = torch.arange(256, dtype=torch.int32).to(torch.uint8).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    fin = np.sort(np.unique(codes[np.isfinite(codes)]))
+    mids = ((fin[1:] + fin[:-1]) / 2).astype(np.float32)
+    x = np.concatenate([x, mids, [0.0, -0.0, 448.0, -448.0, 2.0 ** -9, 2.0 ** -10, 3 * 2.0 ** -11]]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(fp8.e4m3_round(x), ref)
+    assert np.array_equal(fp8.e4m3_round(fin.astype(np.float32)), fin)     # codes are fixed points
+    assert len(fin) == 253                  # 2 x 126 non-zero finite values + one zero
+    assert fin.max() == 448.0 and np.min(fin[fin > 0]) == 2.0 ** -9
+
+
+def test_e4m3_scale_exponent():
+    from oracle import fp8
+    rng = np.random.default_rng(9)
+    for amax in np.ldexp(rng.uniform(0.5, 1.0, 2000), rng.integers(-60, 60, 2000)):
+        e = fp8.scale_exponent(amax)
+        assert amax * 2.0 ** e <= 448.0 < amax * 2.0 ** (e + 1)
+    assert fp8.scale_exponent(448.0) == 0 and fp8.scale_exponent(449.0) == -1
+    assert fp8.scale_exponent(0.875) == 9 and fp8.scale_exponent(0.8751) == 8
+    assert fp8.scale_exponent(0.0) == 0
+
+
+def test_fp8_blur_reduces_to_basis_blur_on_representable_operands():
+    """Operands that are already E4M3 values (times the basis scales) are left
+    unchanged by the quantisation, so the FP8 blur is the plain basis blur."""
+    from oracle import fp8
+    rng = np.random.default_rng(10)
+    K, P, H, W = 3, 5, 9, 11
+    vals = np.array([0.0, 0.25, 0.5, 0.75, 1.0, 1.5, 2.0, 0.125, 0.0625])
+    img = rng.choice(vals, (H, W))
+    basis = rng.choice(vals, (K, P, P)) * np.array([2.0 ** -10, 1.0, 2.0 ** 5])[:, None, None]
+    w = rng.normal(size=(H, W, K))
+    assert np.array_equal(fp8.fp8_blur(img, basis, w), blur.basis_blur(img, basis, w))
+    qb, ex = fp8.quantize_basis(basis)
+    assert np.array_equal(qb, basis)
+    # and a generic basis is changed by at most half an E4M3 step of its scale
+    b = rng.normal(size=(K, P, P))
+    qb, ex = fp8.quantize_basis(b)
+    for k in range(K):
+        step = 2.0 ** (5 - ex[k])           # 448 = 1.75 * 2^8: top binade spacing 2^5
+        assert np.max(np.abs(qb[k] - b[k])) <= step / 2 + 1e-12
