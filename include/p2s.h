@@ -58,7 +58,11 @@ typedef enum {
     P2S_FP32 = 0,     /* FP32 MFMA for network and blur                     */
     P2S_BF16 = 1,     /* BF16 MFMA, FP32 accumulation; network activations
                          enter as a bf16 hi + lo pair, weights w stay FP32   */
-    P2S_FP8E4M3 = 2   /* reserved: FP8 E4M3 blur                            */
+    P2S_FP8E4M3 = 2   /* blur on FP8 E4M3 MFMA (image rounded to E4M3 after
+                         clamping to +-448; basis function k scaled by a power
+                         of two 2^e_k, max |phi_k| 2^e_k <= 448, before
+                         rounding, the scale undone inside the MFMA), FP32
+                         accumulation; the network runs as in P2S_BF16       */
 } p2s_precision;
 
 /* Opaque, immutable, device-resident handles; safe to share across streams. */
@@ -110,8 +114,9 @@ size_t p2s_workspace_bytes(int C, int H, int W, int n_zernike, int K, const p2s_
 /* Upload a PSF basis phi_m (Sec. 3.1 Eq. 4, learned by PCA in Sec. 3.2).
  * host_basis: host, float64 [K][P][P]; tap [i][j] sits at offset
  * (i - R, j - R), R = (P-1)/2, and acts as a convolution kernel.
- * K in [1, P2S_MAX_K], P odd in [1, P2S_MAX_P].  The library keeps FP32 and
- * BF16 copies laid out for its MFMA kernels.  *out receives the handle. */
+ * K in [1, P2S_MAX_K], P odd in [1, P2S_MAX_P].  The library keeps FP32,
+ * BF16 and (for P = 8a + 1) FP8 E4M3 copies laid out for its MFMA kernels.
+ * *out receives the handle. */
 int p2s_basis_create(const double* host_basis, int K, int P, p2s_basis_t* out);
 int p2s_basis_destroy(p2s_basis_t basis);
 int p2s_basis_info(p2s_basis_t basis, int* K, int* P);
@@ -148,8 +153,8 @@ int p2s_make_fields(int H, int W, double D_over_r0, int n_zernike, uint64_t seed
 /* Stage 2: the P2S network at every pixel (Sec. 3.3).  Reads planes
  * 2 .. n_zernike-1 of `fields` (device [n_zernike][H][W]); requires
  * n_zernike - 2 == the network's input width.  Writes w: device float32
- * [H*W][K], K = the network's output width.  precision: P2S_FP32 or
- * P2S_BF16. */
+ * [H*W][K], K = the network's output width.  precision: P2S_FP32, or
+ * P2S_BF16 / P2S_FP8E4M3 (both run the network in BF16). */
 int p2s_mlp(p2s_mlp_t mlp, const float* fields, int n_zernike, int H, int W,
             p2s_precision precision, float* w, void* stream);
 
@@ -157,8 +162,8 @@ int p2s_mlp(p2s_mlp_t mlp, const float* fields, int n_zernike, int H, int W,
  *   out_c(x) = sum_k w_k(x) sum_u phi_k(u) image_c(clamp(x - u)),
  * replicate border, the same weights for every channel (Sec. 3.5).
  * image, out: device float32 [C][H][W] (must not overlap); w: device float32
- * [H*W][K] with K = the basis size.  precision: P2S_FP32 (any odd P) or
- * P2S_BF16 (P = 8a + 1, e.g. 17 or 33). */
+ * [H*W][K] with K = the basis size.  precision: P2S_FP32 (any odd P),
+ * P2S_BF16 or P2S_FP8E4M3 (P = 8a + 1, e.g. 17 or 33). */
 int p2s_blur(const float* image, int C, int H, int W, p2s_basis_t basis, const float* w,
              p2s_precision precision, float* out, void* stream);
 

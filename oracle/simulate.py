@@ -4,17 +4,19 @@ basis blur of every colour channel with the same weights -> tilt warp of
 every channel with alpha_2, alpha_3.
 
 ``weights="projection"`` replaces the network by the projection of each
-pixel's exact PSF onto the basis (used to measure truncation error), and
-``exact_blur`` adds the per-pixel pupil-FFT blur of Eq. 3 (tiny frames only).
+pixel's exact PSF onto the basis (used to measure truncation error),
+``exact_blur`` adds the per-pixel pupil-FFT blur of Eq. 3 (tiny frames only),
+and ``blur_operands="fp8"`` feeds the basis blur E4M3-rounded image and basis
+values (the FP8 precision variant; everything else unchanged).
 """
 import numpy as np
 
-from . import blur, fields, mlp, psf, warp
+from . import blur, fields, fp8, mlp, psf, warp
 
 
 def simulate(image: np.ndarray, d_over_r0: float, basis: np.ndarray, Ws=None, bs=None, seed: int = 0,
              n_zernike: int = 35, corr_len: float = 16.0, q: float = 2.0,
-             weights: str = "mlp", exact: bool = False, Np: int = 32):
+             weights: str = "mlp", exact: bool = False, Np: int = 32, blur_operands: str = "exact"):
     img = np.asarray(image, dtype=np.float64)
     if img.ndim == 2:
         img = img[None]
@@ -33,7 +35,12 @@ def simulate(image: np.ndarray, d_over_r0: float, basis: np.ndarray, Ws=None, bs
     else:
         raise ValueError(weights)
     res["w"] = w
-    bl = np.stack([blur.basis_blur(img[c], basis, w.reshape(H, W, K)) for c in range(C)])
+    if blur_operands == "exact":
+        bl = np.stack([blur.basis_blur(img[c], basis, w.reshape(H, W, K)) for c in range(C)])
+    elif blur_operands == "fp8":
+        bl = np.stack([fp8.fp8_blur(img[c], basis, w.reshape(H, W, K)) for c in range(C)])
+    else:
+        raise ValueError(blur_operands)
     res["blurred"] = bl
     res["out"] = np.stack([warp.tilt_warp(bl[c], F[0], F[1], q) for c in range(C)])
     if exact:

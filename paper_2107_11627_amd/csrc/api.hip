@@ -224,41 +224,78 @@ int pack_basis(const double* hb, int K, int P, Basis* B) {
             }
     B->bf16_ok = (P % 8 == 1 && P >= 9);
     std::vector<uint16_t> h16;
+    std::vector<uint8_t> h8;
+    std::vector<int> sc;
     if (B->bf16_ok) {
         const int A8 = P / 8, NROW = P * A8, NCOL = (P + 7) / 8;
+        // tap of chunk ch, element e (row chunks, then the last tap column, then zero)
+        auto chunk_tap = [&](int k, int ch, int e) -> double {
+            if (ch < NROW) return tap(k, ch / A8 - R, (ch % A8) * 8 - R + e);
+            if (ch < NROW + NCOL) return tap(k, -R + 8 * (ch - NROW) + e, R);
+            return 0.0;
+        };
         B->t32 = (NROW + NCOL + 3) / 4;
         h16.assign((size_t)(B->t32 + 2) * B->nmb * 64 * 8, 0);   // two zero steps: prefetch slack
         for (int t = 0; t < B->t32; ++t)
             for (int mb = 0; mb < B->nmb; ++mb)
                 for (int L = 0; L < 64; ++L)
-                    for (int e = 0; e < 8; ++e) {
-                        const int ch = 4 * t + L / 16, k = 16 * mb + L % 16;
-                        double v = 0.0;
-                        if (ch < NROW) v = tap(k, ch / A8 - R, (ch % A8) * 8 - R + e);
-                        else if (ch < NROW + NCOL) v = tap(k, -R + 8 * (ch - NROW) + e, R);
-                        h16[(((size_t)t * B->nmb + mb) * 64 + L) * 8 + e] = f32_to_bf16_rne((float)v);
-                    }
+                    for (int e = 0; e < 8; ++e)
+                        h16[(((size_t)t * B->nmb + mb) * 64 + L) * 8 + e] =
+                            f32_to_bf16_rne((float)chunk_tap(16 * mb + L % 16, 4 * t + L / 16, e));
+        // FP8: per-basis power-of-two scale from the float32 taps
+        sc.assign((size_t)16 * B->nmb, 127);
+        std::vector<int> ex(K, 0);
+        for (int k = 0; k < K; ++k) {
+            float amax = 0.0f;
+            for (int u = 0; u < U; ++u) amax = std::max(amax, std::fabs((float)hb[(size_t)k * U + u]));
+            ex[k] = e4m3_scale_exponent(amax);
+            sc[k] = 127 - ex[k];
+        }
+        B->t128 = (NROW + NCOL + 15) / 16;
+        h8.assign((size_t)(B->t128 + 2) * B->nmb * 64 * 32, 0);  // two zero steps: prefetch slack
+        for (int t = 0; t < B->t128; ++t)
+            for (int mb = 0; mb < B->nmb; ++mb)
+                for (int L = 0; L < 64; ++L) {
+                    const int k = 16 * mb + L % 16;
+                    for (int j = 0; j < 4; ++j)
+                        for (int e = 0; e < 8; ++e) {
+                            const float v = (float)chunk_tap(k, 16 * t + 4 * (L / 16) + j, e);
+                            h8[(((size_t)t * B->nmb + mb) * 64 + L) * 32 + 8 * j + e] =
+                                k < K ? f32_to_e4m3_rne(std::ldexp(v, ex[k])) : 0;
+                        }
+                }
     }
-    hipError_t e = hipMalloc(&B->f32, f32.size() * sizeof(float));
-    if (e != hipSuccess) return fail(P2S_ENOMEM, "hipMalloc basis: %s", hipGetErrorString(e));
-    e = hipMemcpy(B->f32, f32.data(), f32.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        (void)hipFree(B->f32);
-        return hip_fail(e, "upload basis");
-    }
+    B->f32 = nullptr;
     B->bf16 = nullptr;
-    if (B->bf16_ok) {
-        e = hipMalloc(&B->bf16, h16.size() * sizeof(uint16_t));
+    B->fp8 = nullptr;
+    B->fp8_scale = nullptr;
+    auto release = [&] {
+        (void)hipFree(B->f32);
+        (void)hipFree(B->bf16);
+        (void)hipFree(B->fp8);
+        (void)hipFree(B->fp8_scale);
+    };
+    auto upload = [&](void** dst, const void* src, size_t bytes) -> int {
+        hipError_t e = hipMalloc(dst, bytes);
         if (e != hipSuccess) {
-            (void)hipFree(B->f32);
+            *dst = nullptr;
+            release();
             return fail(P2S_ENOMEM, "hipMalloc basis: %s", hipGetErrorString(e));
         }
-        e = hipMemcpy(B->bf16, h16.data(), h16.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+        e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            (void)hipFree(B->f32);
-            (void)hipFree(B->bf16);
+            release();
             return hip_fail(e, "upload basis");
         }
+        return P2S_OK;
+    };
+    int rc = upload((void**)&B->f32, f32.data(), f32.size() * sizeof(float));
+    if (rc) return rc;
+    if (B->bf16_ok) {
+        if ((rc = upload((void**)&B->bf16, h16.data(), h16.size() * sizeof(uint16_t))) ||
+            (rc = upload((void**)&B->fp8, h8.data(), h8.size())) ||
+            (rc = upload((void**)&B->fp8_scale, sc.data(), sc.size() * sizeof(int))))
+            return rc;
     }
     return P2S_OK;
 }
@@ -328,8 +365,7 @@ int pack_mlp(int L, const int* dims, const float* const* W, const float* const* 
 }
 
 int check_prec(p2s_precision prec) {
-    if (prec == P2S_FP32 || prec == P2S_BF16) return P2S_OK;
-    if (prec == P2S_FP8E4M3) return fail(P2S_EUNSUPPORTED, "FP8 E4M3 precision is not available in this build");
+    if (prec == P2S_FP32 || prec == P2S_BF16 || prec == P2S_FP8E4M3) return P2S_OK;
     return fail(P2S_EINVAL, "unknown precision %d", (int)prec);
 }
 
@@ -363,8 +399,8 @@ int blur_impl(const float* img, int C, int H, int W, const Basis& b, const float
     const size_t n = (size_t)C * H * W * 4;
     if (overlap(img, n, out, n)) return fail(P2S_EINVAL, "image and out overlap");
     if (overlap(w, (size_t)H * W * b.K * 4, out, n)) return fail(P2S_EINVAL, "w and out overlap");
-    if (prec == P2S_BF16 && !b.bf16_ok)
-        return fail(P2S_EUNSUPPORTED, "BF16 blur needs a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", b.P);
+    if (prec != P2S_FP32 && !b.bf16_ok)
+        return fail(P2S_EUNSUPPORTED, "BF16 and FP8 blur need a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", b.P);
     hipError_t e = launch_blur(b, img, C, H, W, w, prec, out, s);
     if (e != hipSuccess) return hip_fail(e, "blur kernel");
     return P2S_OK;
@@ -458,8 +494,8 @@ int batch_create(const p2s_frame* frames, int n, int nz, const Basis& B, const M
         return fail(P2S_EINVAL, "n_zernike - 2 = %d does not match the network input width %d", nz - 2, M.dims[0]);
     if (M.dims[M.L] != B.K)
         return fail(P2S_EINVAL, "network output width %d does not match the basis size K = %d", M.dims[M.L], B.K);
-    if (prec == P2S_BF16 && !B.bf16_ok)
-        return fail(P2S_EUNSUPPORTED, "BF16 blur needs a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", B.P);
+    if (prec != P2S_FP32 && !B.bf16_ok)
+        return fail(P2S_EUNSUPPORTED, "BF16 and FP8 blur need a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", B.P);
     const size_t wbytes = prec == P2S_FP32 ? M.bytes32 : M.bytes16;
     if (wbytes > kMlpLdsBytes)
         return fail(P2S_EUNSUPPORTED, "packed network weights (%zu bytes) exceed the %zu-byte LDS of one workgroup "
@@ -473,7 +509,7 @@ int batch_create(const p2s_frame* frames, int n, int nz, const Basis& B, const M
         rows = opt->blur_tile_rows;
         persistent = opt->persistent;
     }
-    rows = blur_tile_rows(B.nmb, rows);
+    rows = blur_tile_rows(prec, B.nmb, rows);
     BatchLayout L;
     rc = batch_layout(frames, n, nz, B.K, pr, &L);
     if (rc) return rc;
@@ -605,6 +641,34 @@ int batch_launch(const BatchHost* h, hipStream_t s) {
 
 }  // namespace
 
+uint8_t f32_to_e4m3_rne(float x) {
+    const uint8_t sign = std::signbit(x) ? 0x80 : 0x00;
+    double a = std::fabs((double)x);
+    if (std::isnan(a)) return 0x7F;
+    if (a > 448.0) a = 448.0;
+    if (a < 0.015625) {                                   // below 2^-6: subnormal steps of 2^-9
+        const int m = (int)std::nearbyint(a * 512.0);     // ties to even (default rounding mode)
+        return (uint8_t)(sign | (m == 8 ? 0x08 : m));
+    }
+    int e2;
+    std::frexp(a, &e2);                                   // a = f 2^e2, f in [0.5, 1)
+    int E = e2 - 1;                                       // a in [2^E, 2^(E+1))
+    int m = (int)std::nearbyint((std::ldexp(a, -E) - 1.0) * 8.0);
+    if (m == 8) {
+        m = 0;
+        ++E;
+    }
+    return (uint8_t)(sign | ((E + 7) << 3) | m);
+}
+
+int e4m3_scale_exponent(float amax) {
+    if (!(amax > 0.0f)) return 0;
+    int E;
+    const double f = std::frexp((double)amax, &E);        // amax = f 2^E, 448 = 0.875 2^9
+    const int e = f <= 0.875 ? 9 - E : 8 - E;
+    return std::min(127, std::max(-127, e));
+}
+
 uint16_t f32_to_bf16_rne(float x) {
     uint32_t u;
     std::memcpy(&u, &x, 4);
@@ -683,6 +747,8 @@ int p2s_basis_destroy(p2s_basis_t basis) {
     if (!basis) return ok();
     (void)hipFree(basis->b.f32);
     if (basis->b.bf16) (void)hipFree(basis->b.bf16);
+    if (basis->b.fp8) (void)hipFree(basis->b.fp8);
+    if (basis->b.fp8_scale) (void)hipFree(basis->b.fp8_scale);
     delete basis;
     return ok();
 }
@@ -795,8 +861,8 @@ int p2s_simulate(const float* image, int C, int H, int W, double D_over_r0, int 
     if (mlp->m.dims[mlp->m.L] != basis->b.K)
         return fail(P2S_EINVAL, "network output width %d does not match the basis size K = %d",
                     mlp->m.dims[mlp->m.L], basis->b.K);
-    if (precision == P2S_BF16 && !basis->b.bf16_ok)
-        return fail(P2S_EUNSUPPORTED, "BF16 blur needs a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", basis->b.P);
+    if (precision != P2S_FP32 && !basis->b.bf16_ok)
+        return fail(P2S_EUNSUPPORTED, "BF16 and FP8 blur need a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", basis->b.P);
     if (!image || !out || !ws) return fail(P2S_EINVAL, "image, out or workspace is NULL");
     if (!(std::isfinite(D_over_r0) && D_over_r0 >= 0.0)) return fail(P2S_EINVAL, "D/r0 must be finite and >= 0");
     const int Nfy = grid_of(H, pr.corr_len), Nfx = grid_of(W, pr.corr_len);

@@ -290,6 +290,135 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
     }
 }
 
+// ------------------------------------------------------------------- FP8
+// E4M3 operands on v_mfma_scale_f32_16x16x128_f8f6f4.  The LDS holds the same
+// RowPk / ColPk arrangement as BF16 with 8 E4M3 values (8 bytes) per entry.
+// One step covers 16 chunks (128 taps): lane group g supplies chunks
+// 16 t + 4 g + j, j = 0..3, as the 32 bytes of its B operand, and the packed
+// basis supplies the same chunks of its row.  The MFMA multiplies row k by
+// the E8M0 scale 2^-e_k of that basis function, so the accumulators hold the
+// unscaled convolutions and the epilogue is the one of the other precisions.
+// The image is rounded to E4M3 (ties to even) after clamping to +-448.
+__device__ __forceinline__ uint2 pack_e4m3x8(const float* s, int stride) {
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = fminf(fmaxf(s[e * stride], -448.0f), 448.0f);
+    uint32_t lo = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false) & 0xFFFFu;
+    lo |= ((uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], 0, false) & 0xFFFFu) << 16;
+    uint32_t hi = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], 0, false) & 0xFFFFu;
+    hi |= ((uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], 0, false) & 0xFFFFu) << 16;
+    return make_uint2(lo, hi);
+}
+
+template <int P, int NMB, int NBLK>
+__device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int H, int W,
+                                              const uint4* __restrict__ bp, const int* __restrict__ scale, int K,
+                                              const float* __restrict__ w, float* __restrict__ out, int tiles_x,
+                                              int tile, int c) {
+    constexpr int R = (P - 1) / 2;
+    constexpr int A8 = P / 8;
+    constexpr int NROW = P * A8;
+    constexpr int NCOL = (P + 7) / 8;
+    constexpr int T128 = (NROW + NCOL + 15) / 16;
+    constexpr int TY = NBLK * 2;
+    constexpr int PITCH = kTX + 8 * (A8 - 1);
+    constexpr int PH = TY + 2 * R;
+    constexpr int QH = TY + 8 * (NCOL - 1);
+    constexpr int NR = PH > QH ? PH : QH;
+    constexpr int SW = kTX + 2 * R;
+    constexpr int SH = (QH + 7 > PH ? QH + 7 : PH);
+    static_assert(P == 8 * A8 + 1, "fp8 layout needs P = 8a + 1");
+    __shared__ uint2 rowpk8[NR * PITCH];
+    __shared__ uint2 colpk8[NR * PITCH];
+    __shared__ float stage8[SH * SW];
+
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int x0 = tx * kTX, y0 = ty * TY;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, m = lane & 15;
+    constexpr int RPW = NBLK / 2;
+    const int lyw = wave * RPW;
+    const size_t HW = (size_t)H * W;
+
+    const float* ic = img + c * HW;
+    __syncthreads();                              // previous item of a persistent workgroup done with LDS
+    stage_window<14>(stage8, SW, ic, H, W, y0 - R, x0 - R, SH, SW);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < PH * PITCH; idx += blockDim.x) {
+        const int r = idx / PITCH, p = idx - r * PITCH;
+        rowpk8[idx] = pack_e4m3x8(stage8 + r * SW + p, 1);
+    }
+    for (int idx = threadIdx.x; idx < QH * kTX; idx += blockDim.x) {
+        const int r = idx / kTX, q = idx - r * kTX;
+        colpk8[r * PITCH + q] = pack_e4m3x8(stage8 + r * SW + q + 2 * R, SW);
+    }
+    __syncthreads();
+    int sc[NMB];
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb) sc[mb] = scale[16 * mb + m];
+    floatx4 acc[NBLK][NMB];
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb) acc[b][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int pbase = lyw * PITCH + m;
+    auto chunk_src = [&](int ch) -> const uint2* {
+        if (ch < NROW) {
+            const int dy = ch / A8 - R, dx0 = (ch % A8) * 8 - R;
+            return rowpk8 + pbase + (dy + R) * PITCH + (dx0 + R);
+        }
+        int q = ch - NROW;
+        if (q >= NCOL) q = 0;                     // zero chunk: any valid entry
+        return colpk8 + pbase + 8 * q * PITCH;
+    };
+    // Register budget: the A operands (8 registers per basis block) of the
+    // next step are loaded at the start of a step into the second of two
+    // sets; the B operands are streamed per pixel block, the LDS reads of
+    // block b + 1 issued before the MFMAs of block b (sched barriers keep the
+    // compiler from hoisting all of a step's reads).  Loads past the last step
+    // read a zero basis step and a valid LDS entry.
+    const intx8* bp8 = reinterpret_cast<const intx8*>(bp);
+    intx8 a0[NMB], a1[NMB];
+    auto load_a = [&](int t, intx8* av) {
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb) av[mb] = bp8[((size_t)t * NMB + mb) * 64 + lane];
+    };
+    auto load_b = [&](const uint2* const* src, int b, intx8& pv) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint2 v = src[j][(b >> 1) * PITCH + (b & 1) * 16];
+            pv[2 * j] = (int)v.x;
+            pv[2 * j + 1] = (int)v.y;
+        }
+    };
+    auto step = [&](int t, const intx8* av, intx8* an) {
+        load_a(t + 1, an);
+        const uint2* src[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) src[j] = chunk_src(16 * t + 4 * g + j);
+        intx8 pb[2];
+        load_b(src, 0, pb[0]);
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b) {
+            if (b + 1 < NBLK) load_b(src, b + 1, pb[(b + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+                acc[b][mb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av[mb], pb[b & 1], acc[b][mb], 0, 0, 0,
+                                                                             sc[mb], 0, 127);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    load_a(0, a0);
+#pragma unroll 1
+    for (int t = 0; t + 1 < T128; t += 2) {
+        step(t, a0, a1);
+        step(t + 1, a1, a0);
+    }
+    if constexpr (T128 & 1) step(T128 - 1, a0, a1);
+    epilogue<NMB, NBLK>(acc, w, K, y0 + lyw, x0, H, W, g, m, out + c * HW);
+}
+
 template <int NMB, int NBLK>
 __global__ void __launch_bounds__(256) blur_f32_kernel(const float* __restrict__ img, int H, int W, int P,
                                                        const float* __restrict__ bp, int t4, int K,
@@ -304,6 +433,14 @@ __global__ void __launch_bounds__(256) blur_bf16_kernel(const float* __restrict_
                                                         const float* __restrict__ w, float* __restrict__ out,
                                                         int tiles_x) {
     blur_bf16_tile<P, NMB, NBLK>(img, H, W, bp, K, w, out, tiles_x, blockIdx.x, blockIdx.y);
+}
+
+template <int P, int NMB, int NBLK>
+__global__ void __launch_bounds__(256) blur_fp8_kernel(const float* __restrict__ img, int H, int W,
+                                                       const uint4* __restrict__ bp, const int* __restrict__ scale,
+                                                       int K, const float* __restrict__ w, float* __restrict__ out,
+                                                       int tiles_x) {
+    blur_fp8_tile<P, NMB, NBLK>(img, H, W, bp, scale, K, w, out, tiles_x, blockIdx.x, blockIdx.y);
 }
 
 // Batched, persistent forms over the (frame, channel, tile) list.
@@ -335,6 +472,21 @@ __global__ void __launch_bounds__(256) blur_bf16_batch(const FrameDesc* __restri
     }
 }
 
+template <int P, int NMB, int NBLK>
+__global__ void __launch_bounds__(256) blur_fp8_batch(const FrameDesc* __restrict__ fr, const int* __restrict__ first,
+                                                      int n, const uint4* __restrict__ bp,
+                                                      const int* __restrict__ scale, int K) {
+    const int total = first[n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int f = find_frame(first, n, item);
+        const FrameDesc& d = fr[f];
+        const int l = item - first[f];
+        const int nt = d.tiles_x * d.tiles_y;
+        const int c = l / nt;
+        blur_fp8_tile<P, NMB, NBLK>(d.image, d.H, d.W, bp, scale, K, d.w, d.blurred, d.tiles_x, l - c * nt, c);
+    }
+}
+
 template <int NMB>
 hipError_t launch_f32(const Basis& b, const float* img, int C, int H, int W, const float* w, float* out,
                       hipStream_t s) {
@@ -346,29 +498,36 @@ hipError_t launch_f32(const Basis& b, const float* img, int C, int H, int W, con
     return hipGetLastError();
 }
 
+// BF16 and FP8 share the chunk layout, the tile shapes and the dispatch.
 template <int P, int NMB>
-hipError_t launch_bf16(const Basis& b, const float* img, int C, int H, int W, const float* w, float* out,
-                       hipStream_t s) {
-    constexpr int NBLK = NMB <= 7 ? 8 : 4;
-    constexpr int TY = NBLK * 2;
+hipError_t launch_lowp(const Basis& b, p2s_precision prec, const float* img, int C, int H, int W, const float* w,
+                       float* out, hipStream_t s) {
+    const int TY = blur_tile_rows(prec, NMB, 16);
     const int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + TY - 1) / TY;
-    hipLaunchKernelGGL((blur_bf16_kernel<P, NMB, NBLK>), dim3(tiles_x * tiles_y, C), dim3(256), 0, s, img, H, W,
-                       reinterpret_cast<const uint4*>(b.bf16), b.K, w, out, tiles_x);
+    const dim3 grid(tiles_x * tiles_y, C);
+    if (prec == P2S_BF16) {
+        constexpr int NBLK = NMB <= 7 ? 8 : 4;
+        hipLaunchKernelGGL((blur_bf16_kernel<P, NMB, NBLK>), grid, dim3(256), 0, s, img, H, W,
+                           reinterpret_cast<const uint4*>(b.bf16), b.K, w, out, tiles_x);
+    } else {
+        hipLaunchKernelGGL((blur_fp8_kernel<P, NMB, 4>), grid, dim3(256), 0, s, img, H, W,
+                           reinterpret_cast<const uint4*>(b.fp8), b.fp8_scale, b.K, w, out, tiles_x);
+    }
     return hipGetLastError();
 }
 
 template <int P>
-hipError_t dispatch_bf16(const Basis& b, const float* img, int C, int H, int W, const float* w, float* out,
-                         hipStream_t s) {
+hipError_t dispatch_lowp(const Basis& b, p2s_precision prec, const float* img, int C, int H, int W, const float* w,
+                         float* out, hipStream_t s) {
     switch (b.nmb) {
-        case 1: return launch_bf16<P, 1>(b, img, C, H, W, w, out, s);
-        case 2: return launch_bf16<P, 2>(b, img, C, H, W, w, out, s);
-        case 3: return launch_bf16<P, 3>(b, img, C, H, W, w, out, s);
-        case 4: return launch_bf16<P, 4>(b, img, C, H, W, w, out, s);
-        case 5: return launch_bf16<P, 5>(b, img, C, H, W, w, out, s);
-        case 6: return launch_bf16<P, 6>(b, img, C, H, W, w, out, s);
-        case 7: return launch_bf16<P, 7>(b, img, C, H, W, w, out, s);
-        case 8: return launch_bf16<P, 8>(b, img, C, H, W, w, out, s);
+        case 1: return launch_lowp<P, 1>(b, prec, img, C, H, W, w, out, s);
+        case 2: return launch_lowp<P, 2>(b, prec, img, C, H, W, w, out, s);
+        case 3: return launch_lowp<P, 3>(b, prec, img, C, H, W, w, out, s);
+        case 4: return launch_lowp<P, 4>(b, prec, img, C, H, W, w, out, s);
+        case 5: return launch_lowp<P, 5>(b, prec, img, C, H, W, w, out, s);
+        case 6: return launch_lowp<P, 6>(b, prec, img, C, H, W, w, out, s);
+        case 7: return launch_lowp<P, 7>(b, prec, img, C, H, W, w, out, s);
+        case 8: return launch_lowp<P, 8>(b, prec, img, C, H, W, w, out, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -384,7 +543,8 @@ const void* f32_batch_fn(int rows) {
 }
 
 template <int P, int NMB>
-const void* bf16_batch_fn(int rows) {
+const void* lowp_batch_fn(p2s_precision prec, int rows) {
+    if (prec == P2S_FP8E4M3) return (const void*)blur_fp8_batch<P, NMB, 4>;
     if constexpr (NMB <= 7) {
         if (rows == 16) return (const void*)blur_bf16_batch<P, NMB, 8>;
     }
@@ -392,16 +552,16 @@ const void* bf16_batch_fn(int rows) {
 }
 
 template <int P>
-const void* bf16_batch_fn_p(int nmb, int rows) {
+const void* lowp_batch_fn_p(p2s_precision prec, int nmb, int rows) {
     switch (nmb) {
-        case 1: return bf16_batch_fn<P, 1>(rows);
-        case 2: return bf16_batch_fn<P, 2>(rows);
-        case 3: return bf16_batch_fn<P, 3>(rows);
-        case 4: return bf16_batch_fn<P, 4>(rows);
-        case 5: return bf16_batch_fn<P, 5>(rows);
-        case 6: return bf16_batch_fn<P, 6>(rows);
-        case 7: return bf16_batch_fn<P, 7>(rows);
-        case 8: return bf16_batch_fn<P, 8>(rows);
+        case 1: return lowp_batch_fn<P, 1>(prec, rows);
+        case 2: return lowp_batch_fn<P, 2>(prec, rows);
+        case 3: return lowp_batch_fn<P, 3>(prec, rows);
+        case 4: return lowp_batch_fn<P, 4>(prec, rows);
+        case 5: return lowp_batch_fn<P, 5>(prec, rows);
+        case 6: return lowp_batch_fn<P, 6>(prec, rows);
+        case 7: return lowp_batch_fn<P, 7>(prec, rows);
+        case 8: return lowp_batch_fn<P, 8>(prec, rows);
         default: return nullptr;
     }
 }
@@ -420,22 +580,28 @@ const void* blur_batch_fn(const Basis& b, p2s_precision prec, int rows) {
             default: return nullptr;
         }
     }
-    if (!b.bf16_ok) return nullptr;
+    if (!b.bf16_ok || (prec != P2S_BF16 && prec != P2S_FP8E4M3)) return nullptr;
     switch (b.P) {
-        case 9: return bf16_batch_fn_p<9>(b.nmb, rows);
-        case 17: return bf16_batch_fn_p<17>(b.nmb, rows);
-        case 25: return bf16_batch_fn_p<25>(b.nmb, rows);
-        case 33: return bf16_batch_fn_p<33>(b.nmb, rows);
+        case 9: return lowp_batch_fn_p<9>(prec, b.nmb, rows);
+        case 17: return lowp_batch_fn_p<17>(prec, b.nmb, rows);
+        case 25: return lowp_batch_fn_p<25>(prec, b.nmb, rows);
+        case 33: return lowp_batch_fn_p<33>(prec, b.nmb, rows);
         default: return nullptr;
     }
 }
 
 }  // namespace
 
-int blur_tile_rows(int nmb, int preferred) { return (nmb <= 7 && preferred == 16) ? 16 : 8; }
+// Output rows per blur work item: 16 (8 pixel blocks per wave) unless the
+// accumulators and operands of a wave would not fit its registers: K > 112
+// in FP32 and BF16, and always in FP8 (its operands are twice as wide).
+int blur_tile_rows(p2s_precision prec, int nmb, int preferred) {
+    if (prec == P2S_FP8E4M3) return 8;
+    return (nmb <= 7 && preferred == 16) ? 16 : 8;
+}
 
 int blur_batch_resident(const Basis& b, p2s_precision prec, int rows) {
-    const void* fn = blur_batch_fn(b, prec, blur_tile_rows(b.nmb, rows));
+    const void* fn = blur_batch_fn(b, prec, blur_tile_rows(prec, b.nmb, rows));
     return fn ? resident_workgroups(fn, 256, 0) : 0;
 }
 
@@ -448,11 +614,17 @@ hipError_t launch_blur_batch(const Basis& b, const BatchLaunch& bl, p2s_precisio
     int n = bl.n, P = b.P, t4 = b.t4, K = b.K;
     const float* bp32 = b.f32;
     const uint4* bp16 = reinterpret_cast<const uint4*>(b.bf16);
+    const uint4* bp8 = reinterpret_cast<const uint4*>(b.fp8);
+    const int* sc8 = b.fp8_scale;
     if (prec == P2S_FP32) {
         void* args[] = {&fr, &first, &n, &P, &bp32, &t4, &K};
         return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(256), args, 0, s);
     }
-    void* args[] = {&fr, &first, &n, &bp16, &K};
+    if (prec == P2S_BF16) {
+        void* args[] = {&fr, &first, &n, &bp16, &K};
+        return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(256), args, 0, s);
+    }
+    void* args[] = {&fr, &first, &n, &bp8, &sc8, &K};
     return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(256), args, 0, s);
 }
 
@@ -472,10 +644,10 @@ hipError_t launch_blur(const Basis& b, const float* img, int C, int H, int W, co
         }
     }
     switch (b.P) {
-        case 9: return dispatch_bf16<9>(b, img, C, H, W, w, out, s);
-        case 17: return dispatch_bf16<17>(b, img, C, H, W, w, out, s);
-        case 25: return dispatch_bf16<25>(b, img, C, H, W, w, out, s);
-        case 33: return dispatch_bf16<33>(b, img, C, H, W, w, out, s);
+        case 9: return dispatch_lowp<9>(b, prec, img, C, H, W, w, out, s);
+        case 17: return dispatch_lowp<17>(b, prec, img, C, H, W, w, out, s);
+        case 25: return dispatch_lowp<25>(b, prec, img, C, H, W, w, out, s);
+        case 33: return dispatch_lowp<33>(b, prec, img, C, H, W, w, out, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -14,6 +14,7 @@ namespace p2s {
 // ------------------------------------------------------------------ types
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
 
 // Device copy of a PSF basis, laid out as MFMA A-operands (rows = basis
 // functions in blocks of 16, reduction = PSF taps).  Taps are stored in
@@ -34,6 +35,14 @@ struct Basis {
     int t32;
     int bf16_ok;
     uint16_t* bf16;
+    // FP8 E4M3 (v_mfma_scale_f32_16x16x128_f8f6f4): [t128][nmb][64][32] bytes;
+    // lane L of step t supplies chunks 16 t + 4 (L/16) + j, j = 0..3, as bytes
+    // 8 j .. 8 j + 7 (same chunk numbering as BF16).  Basis k is stored as
+    // E4M3(phi_k * 2^e_k); fp8_scale[k] = 127 - e_k is the E8M0 code of
+    // 2^-e_k that the MFMA applies to row k (127, i.e. 1, for padding rows).
+    int t128;
+    uint8_t* fp8;
+    int* fp8_scale;       // [16 nmb]
 };
 
 struct Mlp {
@@ -129,7 +138,7 @@ hipError_t launch_mlp_batch(const Mlp& m, const BatchLaunch& bl, p2s_precision p
 hipError_t launch_blur_batch(const Basis& b, const BatchLaunch& bl, p2s_precision prec, hipStream_t s);
 hipError_t launch_warp_batch(const BatchLaunch& bl, double scale, hipStream_t s);
 int mlp_pixels_per_group();
-int blur_tile_rows(int nmb, int preferred);
+int blur_tile_rows(p2s_precision prec, int nmb, int preferred);
 // Workgroups of each batched kernel the whole device holds at once.
 int fields_batch_resident(bool cols, size_t lds);
 int mlp_batch_resident(const Mlp& m, p2s_precision prec);
@@ -156,6 +165,8 @@ hipError_t launch_warp(const float* in, int C, int H, int W, const float* tilt, 
 
 // --------------------------------------------------------- host helpers
 uint16_t f32_to_bf16_rne(float x);
+uint8_t f32_to_e4m3_rne(float x);     // OCP E4M3, ties to even, |x| clamped to 448
+int e4m3_scale_exponent(float amax);  // largest e with amax 2^e <= 448 (0 for 0), within +-127
 
 // ------------------------------------------------------- device helpers
 __device__ __forceinline__ uint32_t bf16_bits_rne(float x) {

@@ -74,7 +74,7 @@ def small_batch():
     return imgs, d, seeds
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 def test_batch_equals_solo(p2s, small_sim, prec):
     sim = small_sim[0]
     imgs, d, seeds = small_batch()
@@ -174,8 +174,8 @@ def test_batch_empty_and_errors(p2s, small_sim):
         p2s.simulate_batch(dimgs, d[:3], seeds[:3], sim.basis, sim.net, "bf16", outs, ws[:4096])
     assert e.value.code == p2s.P2S_EINVAL and "workspace" in str(e.value)
     with pytest.raises(p2s.P2SError) as e:
-        p2s.simulate_batch(dimgs, d[:3], seeds[:3], sim.basis, sim.net, "fp8", outs, ws)
-    assert e.value.code == p2s.P2S_EUNSUPPORTED
+        p2s.simulate_batch(dimgs, d[:3], seeds[:3], sim.basis, sim.net, 7, outs, ws)
+    assert e.value.code == p2s.P2S_EINVAL
     with pytest.raises(p2s.P2SError) as e:
         p2s.Batch(dimgs, outs, d[:3], seeds[:3], sim.basis, sim.net, "bf16", ws, blur_tile_rows=12)
     assert e.value.code == p2s.P2S_EINVAL
@@ -202,7 +202,8 @@ def test_batch256_full_size_sampled(p2s, big_sim):
     run_workload_sampled(p2s, big_sim, "batch256", "bf16", [0, 17, 63])
 
 
-def test_ragged_full_size_sampled(p2s, big_sim):
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_ragged_full_size_sampled(p2s, big_sim, prec):
     wl = S.workload("ragged")
     big = max(range(len(wl.frames)), key=lambda i: wl.frames[i].H * wl.frames[i].W * wl.frames[i].C)
-    run_workload_sampled(p2s, big_sim, "ragged", "bf16", [0, 1, 199, big])
+    run_workload_sampled(p2s, big_sim, "ragged", prec, [0, 1, 199, big])

@@ -17,6 +17,7 @@ import p2s_synth as S
 from oracle import basis as obasis
 from oracle import blur as oblur
 from oracle import fields as ofields
+from oracle import fp8 as ofp8
 from oracle import mlp as omlp
 from oracle import philox as ophilox
 from oracle import warp as owarp
@@ -168,6 +169,36 @@ def test_blur_bf16_random_basis(p2s, H, W, C, K, P):
     assert rel_l2(got, ref) < 3e-3
 
 
+# FP8 E4M3: the GPU and the oracle round the same float32 image and basis
+# values to E4M3 (ties to even) with the same per-basis power-of-two scales,
+# so the two differ only by the MFMA's FP32 accumulation: 1e-4 rel-L2.  The
+# error of the FP8 variant itself (against unrounded operands) is reported and
+# bounded at 5e-2 (3 mantissa bits: 2^-4 relative per operand).
+@pytest.mark.parametrize("H,W,C,K,P,src", [(37, 45, 2, 20, 17, "random"), (50, 70, 3, 10, 9, "random"),
+                                           (33, 65, 1, 128, 33, "random"), (40, 41, 1, 7, 25, "random"),
+                                           (128, 128, 1, 16, 17, "single128"), (96, 80, 2, 100, 33, "single512")])
+def test_blur_fp8(p2s, H, W, C, K, P, src):
+    if src == "random":
+        basis = np.random.default_rng(K + P).normal(size=(K, P, P)) / P
+        basis *= np.ldexp(1.0, np.random.default_rng(K).integers(-20, 5, K))[:, None, None]   # wide scale range
+    else:
+        basis = oracle_basis(src)
+    rng = np.random.default_rng(H * W)
+    img = rng.random((C, H, W)).astype(np.float32)
+    img[:, :3, :3] = 0.0                                   # zeros and subnormal-range values
+    img[:, 3, :5] = np.float32(1e-3)
+    w = rng.normal(size=(H * W, K)).astype(np.float32)
+    out = torch.empty((C, H, W), dtype=torch.float32, device="cuda")
+    p2s.blur(dev(img), p2s.Basis(basis), dev(w), "fp8", out)
+    got = host(out)
+    ref_q = np.stack([ofp8.fp8_blur(img[c], basis, w.reshape(H, W, K)) for c in range(C)])
+    ref = np.stack([oblur.basis_blur(img[c], basis, w.reshape(H, W, K)) for c in range(C)])
+    eq, ee = rel_l2(got, ref_q), rel_l2(got, ref)
+    print(f"\nfp8 blur {H}x{W}x{C} K={K} P={P} {src}: vs E4M3-operand oracle {eq:.2e}, vs exact operands {ee:.2e}")
+    assert eq < 1e-4
+    assert ee < 5e-2
+
+
 @pytest.mark.parametrize("name", ["single128", "single512"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_blur_learned_basis(p2s, name, prec):
@@ -235,6 +266,25 @@ def test_simulate_workload(p2s, name, prec):
     assert err < (1e-5 if prec == "fp32" else 3e-3)
 
 
+@pytest.mark.parametrize("name", ["single128", "single512"])
+def test_simulate_fp8(p2s, name):
+    """FP8 blur (network in BF16) end to end: against the oracle with E4M3 blur
+    operands within the BF16 bound (the network's BF16 error dominates), and
+    the FP8 variant's own error against the exact oracle reported."""
+    wl = S.workload(name)
+    f = wl.frames[0]
+    basis = oracle_basis(name)
+    Ws, bs = wl.mlp()
+    img = f.image()
+    got = run_sim(p2s, img, f.d_over_r0, basis, Ws, bs, f.field_seed, "fp8")
+    ref_q = osimulate(img, f.d_over_r0, basis, Ws, bs, seed=f.field_seed, blur_operands="fp8")["out"]
+    ref = osimulate(img, f.d_over_r0, basis, Ws, bs, seed=f.field_seed)["out"]
+    eq, ee = rel_l2(got, ref_q), rel_l2(got, ref)
+    print(f"\n{name} fp8 end-to-end rel-L2: vs E4M3-operand oracle {eq:.3e}, vs FP64 oracle {ee:.3e}")
+    assert eq < 3e-3
+    assert ee < 5e-2
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_simulate_rgb_ragged_with_bias(p2s, prec):
     wl = S.workload("single128")
@@ -266,8 +316,8 @@ def test_errors_through_binding(p2s):
     sim = p2s.Simulator(basis, Ws, bs, n_zernike=35)
     img = dev(wl.frames[0].image())
     with pytest.raises(p2s.P2SError) as e:
-        p2s.simulate(img, 1.5, sim.basis, sim.net, 1, "fp8", torch.empty_like(img), sim.workspace(1, 128, 128))
-    assert e.value.code == p2s.P2S_EUNSUPPORTED
+        p2s.simulate(img, 1.5, sim.basis, sim.net, 1, 7, torch.empty_like(img), sim.workspace(1, 128, 128))
+    assert e.value.code == p2s.P2S_EINVAL
     with pytest.raises(p2s.P2SError) as e:
         p2s.simulate(img, 1.5, sim.basis, sim.net, 1, "fp32", torch.empty_like(img), sim.workspace(1, 128, 128),
                      n_zernike=20)
@@ -276,6 +326,7 @@ def test_errors_through_binding(p2s):
     with pytest.raises(p2s.P2SError):
         p2s.simulate(img, 1.5, sim.basis, sim.net, 1, "fp32", torch.empty_like(img), small_ws)
     b5 = p2s.Basis(np.ones((16, 5, 5)) / 25)
-    with pytest.raises(p2s.P2SError) as e:
-        p2s.blur(img, b5, torch.zeros((128 * 128, 16), device="cuda"), "bf16", torch.empty_like(img))
-    assert e.value.code == p2s.P2S_EUNSUPPORTED
+    for prec in ("bf16", "fp8"):
+        with pytest.raises(p2s.P2SError) as e:
+            p2s.blur(img, b5, torch.zeros((128 * 128, 16), device="cuda"), prec, torch.empty_like(img))
+        assert e.value.code == p2s.P2S_EUNSUPPORTED
