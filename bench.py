@@ -10,6 +10,7 @@ before timing starts; every step draws new fields (seed 1000 + step).
 Printed: ONE JSON line on stdout (progress goes to stderr) with
   value        BF16 frames/s (blur and network on BF16 MFMA, FP32 accumulate)
   fp32         the same for the plain FP32 path
+  fp8          the same with the blur on FP8 E4M3 MFMA (network BF16)
   latency      p50/p99 single-frame latency, each frame synchronised
   stages_us    per-stage device time (events around each ABI call)
   roofline     dominant kernel (BF16 fused blur) against the BF16 MFMA peak
@@ -30,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP8_TFLOPS = 5000.0
 PEAK_HBM_GBS = 8000.0
 
 
@@ -125,6 +127,7 @@ def batch_section(args, torch, p2s, S, pbasis):
     Ws, bs = wl0.mlp()
     sim = p2s.Simulator(basis, Ws, bs, n_zernike=wl0.n_zernike)
     out = {}
+    samples = {}
     for name in ("batch256", "ragged"):
         wl = S.workload(name)
         t0 = time.perf_counter()
@@ -137,7 +140,13 @@ def batch_section(args, torch, p2s, S, pbasis):
         outs = [torch.empty_like(im) for im in imgs]
         ws = sim.batch_workspace(shapes)
         rec = {"frames": len(imgs), "megapixels_x_channels": mpix, "workspace_GiB": ws.numel() / 2 ** 30}
-        for prec in ("bf16", "fp32"):
+        # one sampled frame (the smallest): its outputs are kept for the CPU
+        # baseline leg, which compares them with the FP64 oracle
+        ks = min(range(len(imgs)), key=lambda i: shapes[i][0] * shapes[i][1] * shapes[i][2])
+        rec["oracle_sample"] = {"frame": ks, "shape": list(shapes[ks])}
+        samples[name] = {"image": imgs[ks].cpu().numpy(), "d": dd[ks], "seed": seeds[ks], "basis": basis,
+                         "Ws": Ws, "bs": bs, "out": {}}
+        for prec in ("bf16", "fp32", "fp8"):
             opt = autotune.tune(sim, imgs, dd, seeds, prec, outs=outs, ws=ws)
             b = p2s.Batch(imgs, outs, dd, seeds, sim.basis, sim.net, prec, ws, sim.n_zernike, **opt)
             b.upload()
@@ -161,6 +170,7 @@ def batch_section(args, torch, p2s, S, pbasis):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / reps
             items, grid = b.info()
+            samples[name]["out"][prec] = outs[ks].cpu().numpy().astype(np.float64)
             # the same frames one at a time through p2s_simulate (one untimed pass
             # first, so that the workspace has reached its largest size)
             for k, im in enumerate(imgs):
@@ -186,7 +196,7 @@ def batch_section(args, torch, p2s, S, pbasis):
         out[name] = rec
         del imgs, outs, ws
         torch.cuda.empty_cache()
-    return out
+    return out, samples
 
 
 def serving_section(args, torch, p2s, S, pbasis):
@@ -270,7 +280,7 @@ def main():
     ap.add_argument("--mode", choices=["frame", "blur", "copy"], default="frame",
                     help="frame: the benchmark; blur: only the fused blur of the workload (for counter runs); "
                          "copy: a plain device copy of known size (calibrates byte counters)")
-    ap.add_argument("--precision", choices=["bf16", "fp32"], default="bf16", help="precision of --mode blur")
+    ap.add_argument("--precision", choices=["bf16", "fp32", "fp8"], default="bf16", help="precision of --mode blur")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (frames are independent and "
@@ -311,7 +321,7 @@ def main():
 
     res = {}
     outs = {}
-    for prec in ("bf16", "fp32"):
+    for prec in ("bf16", "fp32", "fp8"):
         for i in range(args.warmup):
             frame(1000 + i, prec)
         torch.cuda.synchronize()
@@ -383,8 +393,11 @@ def main():
     fp32_blur_s = res["fp32"]["stages_us"]["blur"] * 1e-6
     fp32_roof = {"bound": "mfma", "achieved": flops / fp32_blur_s / 1e12, "peak": PEAK_FP32_TFLOPS,
                  "frac": flops / fp32_blur_s / 1e12 / PEAK_FP32_TFLOPS}
+    fp8_blur_s = res["fp8"]["stages_us"]["blur"] * 1e-6
+    fp8_roof = {"bound": "mfma", "achieved": flops / fp8_blur_s / 1e12, "peak": PEAK_FP8_TFLOPS,
+                "frac": flops / fp8_blur_s / 1e12 / PEAK_FP8_TFLOPS}
 
-    batches = None if args.no_batches else batch_section(args, torch, p2s, S, pbasis)
+    batches, batch_samples = (None, {}) if args.no_batches else batch_section(args, torch, p2s, S, pbasis)
     serving = None if args.no_serving else serving_section(args, torch, p2s, S, pbasis)
 
     cpu = None
@@ -408,6 +421,11 @@ def main():
                "sample": f"{args.cpu_frames} whole single512 frames (fields, network, blur, warp) in FP64 NumPy",
                "host_cpus": os.cpu_count()}
         errs = {p: float(np.linalg.norm(outs[p] - ref) / np.linalg.norm(ref)) for p in outs}
+        # the sampled frame of each batch workload, every precision, against the oracle
+        for name, smp in batch_samples.items():
+            r = osimulate(smp["image"], smp["d"], smp["basis"], smp["Ws"], smp["bs"], seed=smp["seed"])["out"]
+            for p, got in smp["out"].items():
+                batches[name]["oracle_sample"][p] = float(np.linalg.norm(got - r) / np.linalg.norm(r))
         log(f"[bench] oracle {cpu['value']:.3f} frames/s; rel-L2 vs oracle: " +
             ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
 
@@ -427,10 +445,13 @@ def main():
         "config": {"workload": "single512: 512x512 C=1 blob image, D/r0=3, 35 Zernike planes, K=100 basis of "
                                "33x33, network 33-100-100-100, new field seed per frame",
                    "H": H, "W": W, "C": C, "K": K, "P": P, "n_zernike": NZ, "global_batch": 1},
-        "latency_ms": {"bf16": res["bf16"]["latency_ms"], "fp32": res["fp32"]["latency_ms"]},
+        "latency_ms": {p: res[p]["latency_ms"] for p in res},
         "fp32": {"frames_per_s": res["fp32"]["frames_per_s"], "ms_per_frame": res["fp32"]["ms_per_frame"],
                  "blur_roofline": fp32_roof},
-        "stages_us": {"bf16": res["bf16"]["stages_us"], "fp32": res["fp32"]["stages_us"]},
+        "fp8": {"frames_per_s": res["fp8"]["frames_per_s"], "ms_per_frame": res["fp8"]["ms_per_frame"],
+                "blur_roofline": fp8_roof,
+                "note": "blur on FP8 E4M3 MFMA with per-basis power-of-two scales; network in BF16"},
+        "stages_us": {p: res[p]["stages_us"] for p in res},
         "roofline": roofline,
         "batches": batches,
         "serving": serving,

@@ -167,6 +167,19 @@ int p2s_mlp(p2s_mlp_t mlp, const float* fields, int n_zernike, int H, int W,
 int p2s_blur(const float* image, int C, int H, int W, p2s_basis_t basis, const float* w,
              p2s_precision precision, float* out, void* stream);
 
+/* Stages 2 and 3 in one kernel: the P2S network evaluated inside the blur's
+ * epilogue, so the weights w never exist in memory.  Computes exactly what
+ * p2s_mlp followed by p2s_blur computes with the same precision.  fields:
+ * device [n_zernike][H][W]; image, out: device float32 [C][H][W] (out must
+ * not overlap image or fields).  precision: P2S_BF16 or P2S_FP8E4M3 (network
+ * in BF16); P = 8a + 1.  EUNSUPPORTED when this network does not fit the
+ * fused form: a layer wider than the basis' blocks of 16 (ceil(K/16)), or
+ * packed BF16 weights too large for the LDS left beside the blur tile
+ * (about 78 KB for P = 33 at K <= 112); p2s_simulate then uses the two
+ * stages separately. */
+int p2s_mlp_blur(p2s_mlp_t mlp, const float* fields, int n_zernike, const float* image, int C, int H, int W,
+                 p2s_basis_t basis, p2s_precision precision, float* out, void* stream);
+
 /* Stage 4: tilt warp (Sec. 2.2, 3.3): out_c(y, x) = bilinear sample of in_c
  * at (y + s*tilt[1](y,x), x + s*tilt[0](y,x)), s = 2 q / pi, sample position
  * clamped to the image.  in, out: device float32 [C][H][W] (must not
@@ -174,7 +187,8 @@ int p2s_blur(const float* image, int C, int H, int W, p2s_basis_t basis, const f
 int p2s_warp(const float* in, int C, int H, int W, const float* tilt,
              const p2s_params* params, float* out, void* stream);
 
-/* One frame end to end: fields -> mlp -> blur -> warp, intermediates in ws
+/* One frame end to end: fields -> mlp -> blur -> warp (the network and blur
+ * fused as in p2s_mlp_blur where that form applies), intermediates in ws
  * (device, at least p2s_workspace_bytes).  image, out: device float32
  * [C][H][W].  n_zernike - 2 must equal the network's input width and the
  * network's output width must equal the basis size K. */

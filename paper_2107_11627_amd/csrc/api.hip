@@ -377,7 +377,7 @@ int mlp_impl(const Mlp& m, const float* F, int nz, int H, int W, p2s_precision p
     if (!F || !w) return fail(P2S_EINVAL, "fields or w is NULL");
     int rc = check_prec(prec);
     if (rc) return rc;
-    const size_t wbytes = prec == P2S_FP32 ? m.bytes32 : m.bytes16;
+    const size_t wbytes = prec == P2S_FP32 ? m.bytes32 : network_lds_bytes(m);
     if (wbytes > kMlpLdsBytes)
         return fail(P2S_EUNSUPPORTED, "packed network weights (%zu bytes) exceed the %zu-byte LDS of one workgroup "
                     "in this precision", wbytes, kMlpLdsBytes);
@@ -471,6 +471,7 @@ struct BatchHost {
     void* plan_dev = nullptr;       // start of the workspace
     hipEvent_t uploaded = nullptr;  // recorded after the last upload
     bool upload_pending = false;
+    bool fused = false;             // network evaluated inside the blur kernel
     BatchLaunch bl{};
 };
 
@@ -496,7 +497,7 @@ int batch_create(const p2s_frame* frames, int n, int nz, const Basis& B, const M
         return fail(P2S_EINVAL, "network output width %d does not match the basis size K = %d", M.dims[M.L], B.K);
     if (prec != P2S_FP32 && !B.bf16_ok)
         return fail(P2S_EUNSUPPORTED, "BF16 and FP8 blur need a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", B.P);
-    const size_t wbytes = prec == P2S_FP32 ? M.bytes32 : M.bytes16;
+    const size_t wbytes = prec == P2S_FP32 ? M.bytes32 : network_lds_bytes(M);
     if (wbytes > kMlpLdsBytes)
         return fail(P2S_EUNSUPPORTED, "packed network weights (%zu bytes) exceed the %zu-byte LDS of one workgroup "
                     "in this precision", wbytes, kMlpLdsBytes);
@@ -509,7 +510,9 @@ int batch_create(const p2s_frame* frames, int n, int nz, const Basis& B, const M
         rows = opt->blur_tile_rows;
         persistent = opt->persistent;
     }
-    rows = blur_tile_rows(prec, B.nmb, rows);
+    // The network runs inside the blur unless the caller chose another tile height.
+    const bool fused = blur_mlp_supported(B, M, prec) && rows == 16;
+    rows = fused ? blur_mlp_tile_rows(prec, B.nmb) : blur_tile_rows(prec, B.nmb, rows);
     BatchLayout L;
     rc = batch_layout(frames, n, nz, B.K, pr, &L);
     if (rc) return rc;
@@ -587,9 +590,12 @@ int batch_create(const p2s_frame* frames, int n, int nz, const Basis& B, const M
     bl.lds[ST_COLS] = lds_cols;
     bl.lds[ST_ROWS] = lds_rows;
     for (int st = 0; st < ST_N; ++st) bl.items[st] = (int)tot[st];
+    h->fused = fused;
     if (n > 0) {
         const int res[ST_N] = {fields_batch_resident(true, lds_cols), fields_batch_resident(false, lds_rows),
-                               mlp_batch_resident(M, prec), blur_batch_resident(B, prec, rows), warp_batch_resident()};
+                               mlp_batch_resident(M, prec),
+                               h->fused ? blur_mlp_batch_resident(B, M, prec) : blur_batch_resident(B, prec, rows),
+                               warp_batch_resident()};
         for (int st = 0; st < ST_N; ++st) bl.grid[st] = persistent ? std::min(bl.items[st], res[st]) : bl.items[st];
         hipError_t e = hipHostMalloc(&h->pinned, h->plan_bytes, hipHostMallocDefault);
         if (e != hipSuccess) {
@@ -630,10 +636,15 @@ int batch_launch(const BatchHost* h, hipStream_t s) {
     if (h->n == 0) return P2S_OK;
     hipError_t e = launch_fields_batch(h->bl, s);
     if (e != hipSuccess) return hip_fail(e, "batched field kernels");
-    e = launch_mlp_batch(*h->mlp, h->bl, h->prec, s);
-    if (e != hipSuccess) return hip_fail(e, "batched network kernel");
-    e = launch_blur_batch(*h->basis, h->bl, h->prec, s);
-    if (e != hipSuccess) return hip_fail(e, "batched blur kernel");
+    if (h->fused) {
+        e = launch_blur_mlp_batch(*h->basis, *h->mlp, h->bl, h->prec, s);
+        if (e != hipSuccess) return hip_fail(e, "batched fused network and blur kernel");
+    } else {
+        e = launch_mlp_batch(*h->mlp, h->bl, h->prec, s);
+        if (e != hipSuccess) return hip_fail(e, "batched network kernel");
+        e = launch_blur_batch(*h->basis, h->bl, h->prec, s);
+        if (e != hipSuccess) return hip_fail(e, "batched blur kernel");
+    }
     e = launch_warp_batch(h->bl, h->scale, s);
     if (e != hipSuccess) return hip_fail(e, "batched warp kernel");
     return P2S_OK;
@@ -833,6 +844,35 @@ int p2s_blur(const float* image, int C, int H, int W, p2s_basis_t basis, const f
     return rc ? rc : ok();
 }
 
+int p2s_mlp_blur(p2s_mlp_t mlp, const float* fields, int n_zernike, const float* image, int C, int H, int W,
+                 p2s_basis_t basis, p2s_precision precision, float* out, void* stream) {
+    if (!mlp || !basis) return fail(P2S_EINVAL, "mlp or basis is NULL");
+    int rc = check_frame(C, H, W);
+    if (rc) return rc;
+    rc = check_prec(precision);
+    if (rc) return rc;
+    const Mlp& m = mlp->m;
+    const Basis& b = basis->b;
+    if (n_zernike - 2 != m.dims[0])
+        return fail(P2S_EINVAL, "n_zernike - 2 = %d does not match the network input width %d", n_zernike - 2,
+                    m.dims[0]);
+    if (m.dims[m.L] != b.K)
+        return fail(P2S_EINVAL, "network output width %d does not match the basis size K = %d", m.dims[m.L], b.K);
+    if (!fields || !image || !out) return fail(P2S_EINVAL, "fields, image or out is NULL");
+    const size_t HW = (size_t)H * W, n = (size_t)C * HW * 4;
+    if (overlap(image, n, out, n)) return fail(P2S_EINVAL, "image and out overlap");
+    if (overlap(fields, (size_t)n_zernike * HW * 4, out, n)) return fail(P2S_EINVAL, "fields and out overlap");
+    if (precision == P2S_FP32) return fail(P2S_EUNSUPPORTED, "the fused network and blur runs in BF16 or FP8 only");
+    if (!b.bf16_ok)
+        return fail(P2S_EUNSUPPORTED, "BF16 and FP8 blur need a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", b.P);
+    if (!blur_mlp_supported(b, m, precision))
+        return fail(P2S_EUNSUPPORTED, "fused form needs every network layer within the basis' %d blocks of 16 and "
+                    "its packed BF16 weights (%zu bytes) in the LDS left beside the blur tile", b.nmb, m.bytes16);
+    hipError_t e = launch_blur_mlp(b, m, precision, image, C, H, W, fields, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fused network and blur kernel");
+    return ok();
+}
+
 int p2s_warp(const float* in, int C, int H, int W, const float* tilt, const p2s_params* params, float* out,
              void* stream) {
     Params pr;
@@ -881,10 +921,15 @@ int p2s_simulate(const float* image, int C, int H, int W, double D_over_r0, int 
     float* bl = (float*)(base + L.blurred);
     rc = make_fields_impl(H, W, D_over_r0, n_zernike, seed, pr, F, r2, L.blurred - L.region2, s);
     if (rc) return rc;
-    rc = mlp_impl(mlp->m, F, n_zernike, H, W, precision, r2, s);
-    if (rc) return rc;
-    rc = blur_impl(image, C, H, W, basis->b, r2, precision, bl, s);
-    if (rc) return rc;
+    if (blur_mlp_supported(basis->b, mlp->m, precision)) {     // w never leaves the chip
+        hipError_t e = launch_blur_mlp(basis->b, mlp->m, precision, image, C, H, W, F, bl, s);
+        if (e != hipSuccess) return hip_fail(e, "fused network and blur kernel");
+    } else {
+        rc = mlp_impl(mlp->m, F, n_zernike, H, W, precision, r2, s);
+        if (rc) return rc;
+        rc = blur_impl(image, C, H, W, basis->b, r2, precision, bl, s);
+        if (rc) return rc;
+    }
     rc = warp_impl(bl, C, H, W, F, pr, out, s);
     if (rc) return rc;
     return ok();

@@ -17,7 +17,7 @@
 // Tile: 16 x 32 pixels of one channel per workgroup (4 waves, each 4 rows x
 // 32 pixels = 8 pixel blocks), or 8 x 32 with 4 pixel blocks per wave when
 // K > 112; grid = tiles x channels.
-#include "internal.hpp"
+#include "mlp_block.hpp"
 
 namespace p2s {
 namespace {
@@ -86,6 +86,79 @@ __device__ __forceinline__ void epilogue(const floatx4 (&acc)[NBLK][NMB], const 
         }
     }
 }
+
+// Epilogue sources for the low-precision tiles (called with the accumulators,
+// the wave's first output row, the tile's first column, the lane's (g, m) and
+// the channel).  WFromMemory reads w from the [H*W][K] array; WFromNetwork
+// evaluates the P2S network for each pair of pixel blocks from the field
+// planes (weights in LDS), so that w never exists in memory.  Both produce the
+// same values: the network arithmetic does not depend on which pixels share
+// an MFMA.
+template <int NMB, int NBLK>
+struct WFromMemory {
+    const float* w;
+    int K, H, W;
+    float* out;
+    __device__ __forceinline__ void prefetch(int, int, int) {}
+    __device__ __forceinline__ void begin(int, int, int, int) {}
+    __device__ __forceinline__ void operator()(const floatx4 (&acc)[NBLK][NMB], int yw, int x0, int g, int m,
+                                               int c) const {
+        epilogue<NMB, NBLK>(acc, w, K, yw, x0, H, W, g, m, out + (size_t)c * H * W);
+    }
+};
+
+template <int NMB, int NBLK>
+struct WFromNetwork {
+    const MlpArgs* a;
+    const uint4* lds_w16;
+    const float* bias;
+    const float* fields2;             // plane 2 (alpha_4) of the frame's fields
+    int H, W;
+    float* out;
+    float in[NBLK][2][8];             // the network inputs of the wave's pixel blocks
+    float wv[NBLK][NMB][4];           // the tile's weights, computed before the convolutions
+
+    __device__ __forceinline__ int pixel(int b, int yw, int x0, int m, bool& ok) const {
+        const int y = yw + (b >> 1), x = x0 + (b & 1) * 16 + m;
+        ok = y < H && x < W;
+        return ok ? y * W + x : 0;
+    }
+
+    // At the start of a tile: the field loads, in flight while the image is
+    // staged.
+    __device__ __forceinline__ void prefetch(int yw, int x0, int m) {
+        int pixc[NBLK];
+        bool ok;
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b) pixc[b] = pixel(b, yw, x0, m, ok);
+        mlp_load_inputs<NBLK>(*a, fields2, H * W, pixc, in);
+    }
+
+    // Before the convolutions, while no accumulator is live: the network for
+    // all pixel blocks of the wave at once (every weight read from LDS serves
+    // all of them, and their MFMA chains interleave).
+    __device__ __forceinline__ void begin(int, int, int, int) { mlp_bf16_eval<NMB, NBLK>(*a, lds_w16, bias, in, wv); }
+
+    __device__ __forceinline__ void operator()(const floatx4 (&acc)[NBLK][NMB], int yw, int x0, int g, int m,
+                                               int c) const {
+        float* out_c = out + (size_t)c * H * W;
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b) {
+            bool ok;
+            const int pix = pixel(b, yw, x0, m, ok);
+            float part = 0.0f;
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = 16 * mb + 4 * g + i;
+                    part += (k < a->K) ? acc[b][mb][i] * wv[b][mb][i] : 0.0f;
+                }
+            part = wave_sum4(part);
+            if (ok && g == 0) out_c[pix] = part;
+        }
+    }
+};
 
 // Copy a clamped (replicate-border) window of image rows y_lo.. and columns
 // x_lo.. into LDS, nr x nc floats at pitch ld; loads are issued in batches of
@@ -187,11 +260,12 @@ __device__ __forceinline__ void blur_f32_tile(const float* __restrict__ img, int
 //   RowPk[r][p] = I(y0 - R + r, x0 - R + p + e), e = 0..7   (row chunks)
 //   ColPk[r][q] = I(y0 - R + r + e, x0 + q + R), e = 0..7   (the last tap column)
 // A pixel (ly, lx) reads row chunk (dy, dx0) at RowPk[ly + R + dy][lx + R + dx0]
-// and column chunk q at ColPk[ly + 8 q][lx].  Both share one pitch so that
-// the per-block address delta is the same constant for either kind.
-template <int P, int NMB, int NBLK>
-__device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, int H, int W, const uint4* __restrict__ bp, int K,
-                               const float* __restrict__ w, float* __restrict__ out, int tiles_x, int tile, int c) {
+// and column chunk q at ColPk[ly + 8 q][lx].  RowPk rows hold kTX + 8 (A8 - 1)
+// entries, ColPk rows kTX; a lane's per-pixel-block row step is the pitch of
+// the kind its chunk of the current step comes from.
+template <int P, int NMB, int NBLK, class Epi>
+__device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, int H, int W,
+                                               const uint4* __restrict__ bp, int tiles_x, int tile, int c, Epi&& epi) {
     constexpr int R = (P - 1) / 2;
     constexpr int A8 = P / 8;                    // row chunks per PSF row
     constexpr int NROW = P * A8;
@@ -199,14 +273,14 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
     constexpr int T32 = (NROW + NCOL + 3) / 4;
     constexpr int TY = NBLK * 2;
     constexpr int PITCH = kTX + 8 * (A8 - 1);    // row-chunk positions per row
+    constexpr int CPITCH = kTX;                  // column-chunk positions per row
     constexpr int PH = TY + 2 * R;               // rows of RowPk
     constexpr int QH = TY + 8 * (NCOL - 1);      // rows of ColPk
-    constexpr int NR = PH > QH ? PH : QH;
     constexpr int SW = kTX + 2 * R;              // fp32 staging tile
     constexpr int SH = (QH + 7 > PH ? QH + 7 : PH);
     static_assert(P == 8 * A8 + 1, "bf16 layout needs P = 8a + 1");
-    __shared__ uint4 rowpk[NR * PITCH];
-    __shared__ uint4 colpk[NR * PITCH];
+    __shared__ uint4 rowpk[PH * PITCH];
+    __shared__ uint4 colpk[QH * CPITCH];
     __shared__ float stage[SH * SW];
 
     const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -219,24 +293,21 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
 
     {
         const float* ic = img + c * HW;
+        epi.prefetch(y0 + lyw, x0, m);
         __syncthreads();                          // previous item of a persistent workgroup done with LDS
         stage_window<14>(stage, SW, ic, H, W, y0 - R, x0 - R, SH, SW);
         __syncthreads();
         for (int idx = threadIdx.x; idx < PH * PITCH; idx += blockDim.x) {
             const int r = idx / PITCH, p = idx - r * PITCH;
             const float* s = stage + r * SW + p;
-            uint32_t h[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) h[e] = bf16_bits_rne(s[e]);
-            rowpk[idx] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+            const floatx8 v = {s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7]};
+            rowpk[idx] = __builtin_bit_cast(uint4, to_bf16x8(v));
         }
         for (int idx = threadIdx.x; idx < QH * kTX; idx += blockDim.x) {
             const int r = idx / kTX, q = idx - r * kTX;
             const float* s = stage + r * SW + q + 2 * R;
-            uint32_t h[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) h[e] = bf16_bits_rne(s[e * SW]);
-            colpk[r * PITCH + q] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+            const floatx8 v = {s[0], s[SW], s[2 * SW], s[3 * SW], s[4 * SW], s[5 * SW], s[6 * SW], s[7 * SW]};
+            colpk[r * CPITCH + q] = __builtin_bit_cast(uint4, to_bf16x8(v));
         }
         __syncthreads();
         floatx4 acc[NBLK][NMB];
@@ -244,28 +315,31 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
         for (int b = 0; b < NBLK; ++b)
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb) acc[b][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
-        const int pbase = lyw * PITCH + m;        // pixel block 0 of this lane
-        // B-operand source of chunk 4 t + g for this lane's pixel block 0
-        auto chunk_src = [&](int t) -> const uint4* {
+        // B-operand source of chunk 4 t + g for this lane's pixel block 0, and
+        // the row step of that kind of chunk
+        auto chunk_src = [&](int t, int& step) -> const uint4* {
             const int ch = 4 * t + g;
             if (ch < NROW) {
                 const int dy = ch / A8 - R, dx0 = (ch % A8) * 8 - R;
-                return rowpk + pbase + (dy + R) * PITCH + (dx0 + R);
+                step = PITCH;
+                return rowpk + (lyw + dy + R) * PITCH + m + dx0 + R;
             }
             int q = ch - NROW;
             if (q >= NCOL) q = 0;                 // zero chunk: any valid entry
-            return colpk + pbase + 8 * q * PITCH;
+            step = CPITCH;
+            return colpk + (lyw + 8 * q) * CPITCH + m;
         };
         // Two operand sets alternate: the loads of one step are in flight while
         // the MFMAs of the other run.  Loads one step past the end read a
         // zero basis step and a valid LDS entry.
         uint4 a0[NMB], p0[NBLK], a1[NMB], p1[NBLK];
         auto fetch = [&](int t, uint4* av, uint4* pv) {
-            const uint4* src = chunk_src(t);
+            int step;
+            const uint4* src = chunk_src(t, step);
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb) av[mb] = bp[((size_t)t * NMB + mb) * 64 + lane];
 #pragma unroll
-            for (int b = 0; b < NBLK; ++b) pv[b] = src[(b >> 1) * PITCH + (b & 1) * 16];
+            for (int b = 0; b < NBLK; ++b) pv[b] = src[(b >> 1) * step + (b & 1) * 16];
         };
         auto mma = [&](const uint4* av, const uint4* pv) {
 #pragma unroll
@@ -277,6 +351,7 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
                                                                         acc[b][mb], 0, 0, 0);
             }
         };
+        epi.begin(y0 + lyw, x0, g, m);
         fetch(0, a0, p0);
 #pragma unroll 1
         for (int t = 0; t + 1 < T32; t += 2) {
@@ -286,7 +361,7 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
             mma(a1, p1);
         }
         if constexpr (T32 & 1) mma(a0, p0);
-        epilogue<NMB, NBLK>(acc, w, K, y0 + lyw, x0, H, W, g, m, out + c * HW);
+        epi(acc, y0 + lyw, x0, g, m, c);
     }
 }
 
@@ -310,11 +385,10 @@ __device__ __forceinline__ uint2 pack_e4m3x8(const float* s, int stride) {
     return make_uint2(lo, hi);
 }
 
-template <int P, int NMB, int NBLK>
+template <int P, int NMB, int NBLK, class Epi>
 __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int H, int W,
-                                              const uint4* __restrict__ bp, const int* __restrict__ scale, int K,
-                                              const float* __restrict__ w, float* __restrict__ out, int tiles_x,
-                                              int tile, int c) {
+                                              const uint4* __restrict__ bp, const int* __restrict__ scale,
+                                              int tiles_x, int tile, int c, Epi&& epi) {
     constexpr int R = (P - 1) / 2;
     constexpr int A8 = P / 8;
     constexpr int NROW = P * A8;
@@ -341,6 +415,7 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
     const size_t HW = (size_t)H * W;
 
     const float* ic = img + c * HW;
+    epi.prefetch(y0 + lyw, x0, m);
     __syncthreads();                              // previous item of a persistent workgroup done with LDS
     stage_window<14>(stage8, SW, ic, H, W, y0 - R, x0 - R, SH, SW);
     __syncthreads();
@@ -409,6 +484,7 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
             __builtin_amdgcn_sched_barrier(0);
         }
     };
+    epi.begin(y0 + lyw, x0, g, m);
     load_a(0, a0);
 #pragma unroll 1
     for (int t = 0; t + 1 < T128; t += 2) {
@@ -416,7 +492,7 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
         step(t + 1, a1, a0);
     }
     if constexpr (T128 & 1) step(T128 - 1, a0, a1);
-    epilogue<NMB, NBLK>(acc, w, K, y0 + lyw, x0, H, W, g, m, out + c * HW);
+    epi(acc, y0 + lyw, x0, g, m, c);
 }
 
 template <int NMB, int NBLK>
@@ -432,7 +508,7 @@ __global__ void __launch_bounds__(256) blur_bf16_kernel(const float* __restrict_
                                                         const uint4* __restrict__ bp, int K,
                                                         const float* __restrict__ w, float* __restrict__ out,
                                                         int tiles_x) {
-    blur_bf16_tile<P, NMB, NBLK>(img, H, W, bp, K, w, out, tiles_x, blockIdx.x, blockIdx.y);
+    blur_bf16_tile<P, NMB, NBLK>(img, H, W, bp, tiles_x, blockIdx.x, blockIdx.y, WFromMemory<NMB, NBLK>{w, K, H, W, out});
 }
 
 template <int P, int NMB, int NBLK>
@@ -440,7 +516,8 @@ __global__ void __launch_bounds__(256) blur_fp8_kernel(const float* __restrict__
                                                        const uint4* __restrict__ bp, const int* __restrict__ scale,
                                                        int K, const float* __restrict__ w, float* __restrict__ out,
                                                        int tiles_x) {
-    blur_fp8_tile<P, NMB, NBLK>(img, H, W, bp, scale, K, w, out, tiles_x, blockIdx.x, blockIdx.y);
+    blur_fp8_tile<P, NMB, NBLK>(img, H, W, bp, scale, tiles_x, blockIdx.x, blockIdx.y,
+                                WFromMemory<NMB, NBLK>{w, K, H, W, out});
 }
 
 // Batched, persistent forms over the (frame, channel, tile) list.
@@ -468,7 +545,8 @@ __global__ void __launch_bounds__(256) blur_bf16_batch(const FrameDesc* __restri
         const int l = item - first[f];
         const int nt = d.tiles_x * d.tiles_y;
         const int c = l / nt;
-        blur_bf16_tile<P, NMB, NBLK>(d.image, d.H, d.W, bp, K, d.w, d.blurred, d.tiles_x, l - c * nt, c);
+        blur_bf16_tile<P, NMB, NBLK>(d.image, d.H, d.W, bp, d.tiles_x, l - c * nt, c,
+                                     WFromMemory<NMB, NBLK>{d.w, K, d.H, d.W, d.blurred});
     }
 }
 
@@ -483,7 +561,59 @@ __global__ void __launch_bounds__(256) blur_fp8_batch(const FrameDesc* __restric
         const int l = item - first[f];
         const int nt = d.tiles_x * d.tiles_y;
         const int c = l / nt;
-        blur_fp8_tile<P, NMB, NBLK>(d.image, d.H, d.W, bp, scale, K, d.w, d.blurred, d.tiles_x, l - c * nt, c);
+        blur_fp8_tile<P, NMB, NBLK>(d.image, d.H, d.W, bp, scale, d.tiles_x, l - c * nt, c,
+                                    WFromMemory<NMB, NBLK>{d.w, K, d.H, d.W, d.blurred});
+    }
+}
+
+// Network fused into the blur (BF16 network; BF16 or FP8 blur): persistent
+// workgroups stage the packed network weights into dynamic LDS once, then
+// stride over (channel, tile) items of one frame, or over the (frame,
+// channel, tile) list of a batch.
+template <int P, int NMB, int NBLK, bool FP8>
+__device__ __forceinline__ void fused_item(const float* img, int H, int W, const uint4* bp, const int* scale,
+                                           const MlpArgs& a, const uint4* lds_w16, const float* bias,
+                                           const float* fields2, float* out, int tiles_x, int tile, int c) {
+    WFromNetwork<NMB, NBLK> epi{&a, lds_w16, bias, fields2, H, W, out, {}, {}};
+    if constexpr (FP8)
+        blur_fp8_tile<P, NMB, NBLK>(img, H, W, bp, scale, tiles_x, tile, c, epi);
+    else
+        blur_bf16_tile<P, NMB, NBLK>(img, H, W, bp, tiles_x, tile, c, epi);
+}
+
+template <int P, int NMB, int NBLK, bool FP8>
+__global__ void __launch_bounds__(256) blur_mlp_kernel(const float* __restrict__ img, int C, int H, int W,
+                                                       const uint4* __restrict__ bp, const int* __restrict__ scale,
+                                                       MlpArgs a, const uint4* __restrict__ wg16,
+                                                       const float* __restrict__ bias,
+                                                       const float* __restrict__ fields2, float* __restrict__ out,
+                                                       int tiles_x, int tiles_y) {
+    extern __shared__ uint4 lds_w16[];
+    const float* lds_bias = stage_bf16_network(lds_w16, a, wg16, bias);   // the tile's first barrier publishes them
+    const int nt = tiles_x * tiles_y, total = nt * C;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int c = item / nt;
+        fused_item<P, NMB, NBLK, FP8>(img, H, W, bp, scale, a, lds_w16, lds_bias, fields2, out, tiles_x,
+                                      item - c * nt, c);
+    }
+}
+
+template <int P, int NMB, int NBLK, bool FP8>
+__global__ void __launch_bounds__(256) blur_mlp_batch(const FrameDesc* __restrict__ fr, const int* __restrict__ first,
+                                                      int n, const uint4* __restrict__ bp,
+                                                      const int* __restrict__ scale, MlpArgs a,
+                                                      const uint4* __restrict__ wg16, const float* __restrict__ bias) {
+    extern __shared__ uint4 lds_w16[];
+    const float* lds_bias = stage_bf16_network(lds_w16, a, wg16, bias);
+    const int total = first[n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int f = find_frame(first, n, item);
+        const FrameDesc& d = fr[f];
+        const int l = item - first[f];
+        const int nt = d.tiles_x * d.tiles_y;
+        const int c = l / nt;
+        fused_item<P, NMB, NBLK, FP8>(d.image, d.H, d.W, bp, scale, a, lds_w16, lds_bias,
+                                      d.fields + 2 * (size_t)d.H * d.W, d.blurred, d.tiles_x, l - c * nt, c);
     }
 }
 
@@ -626,6 +756,139 @@ hipError_t launch_blur_batch(const Basis& b, const BatchLaunch& bl, p2s_precisio
     }
     void* args[] = {&fr, &first, &n, &bp8, &sc8, &K};
     return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(256), args, 0, s);
+}
+
+namespace {
+
+// Pixel blocks per wave of the fused BF16 kernel: the blur accumulators
+// (4 NBLK NMB registers) and the network's live values must share the wave's
+// 256 accumulation-capable registers, so wide bases take 12-row or 8-row tiles.
+constexpr int fused_nblk_bf16(int nmb) { return nmb >= 8 ? 2 : (nmb >= 5 ? 4 : 8); }
+
+template <int P, int NMB>
+const void* fused_fn_nmb(p2s_precision prec, bool batch) {
+    if (prec == P2S_FP8E4M3) {
+        if constexpr (NMB <= 4)
+            return batch ? (const void*)blur_mlp_batch<P, NMB, 4, true> : (const void*)blur_mlp_kernel<P, NMB, 4, true>;
+        return nullptr;
+    }
+    constexpr int NBLK = fused_nblk_bf16(NMB);
+    return batch ? (const void*)blur_mlp_batch<P, NMB, NBLK, false> : (const void*)blur_mlp_kernel<P, NMB, NBLK, false>;
+}
+
+template <int P>
+const void* fused_fn_p(p2s_precision prec, int nmb, bool batch) {
+    switch (nmb) {
+        case 1: return fused_fn_nmb<P, 1>(prec, batch);
+        case 2: return fused_fn_nmb<P, 2>(prec, batch);
+        case 3: return fused_fn_nmb<P, 3>(prec, batch);
+        case 4: return fused_fn_nmb<P, 4>(prec, batch);
+        case 5: return fused_fn_nmb<P, 5>(prec, batch);
+        case 6: return fused_fn_nmb<P, 6>(prec, batch);
+        case 7: return fused_fn_nmb<P, 7>(prec, batch);
+        case 8: return fused_fn_nmb<P, 8>(prec, batch);
+        default: return nullptr;
+    }
+}
+
+// The fused kernel for this basis, network and precision, or nullptr when the
+// fused form does not apply: FP32, a PSF side without the low-precision
+// layout, network output blocks other than the basis blocks, or packed BF16
+// network weights that do not fit the LDS left beside the blur tile.
+const void* fused_fn(const Basis& b, const Mlp& m, p2s_precision prec, bool batch) {
+    if (prec == P2S_FP32 || !b.bf16_ok || m.mb != b.nmb || m.dims[m.L] != b.K) return nullptr;
+    const void* fn = nullptr;
+    switch (b.P) {
+        case 9: fn = fused_fn_p<9>(prec, b.nmb, batch); break;
+        case 17: fn = fused_fn_p<17>(prec, b.nmb, batch); break;
+        case 25: fn = fused_fn_p<25>(prec, b.nmb, batch); break;
+        case 33: fn = fused_fn_p<33>(prec, b.nmb, batch); break;
+        default: return nullptr;
+    }
+    if (!fn) return nullptr;
+    hipFuncAttributes attr;
+    if (hipFuncGetAttributes(&attr, fn) != hipSuccess) return nullptr;
+    if (attr.sharedSizeBytes + network_lds_bytes(m) > kMlpLdsBytes) return nullptr;
+    return fn;
+}
+
+}  // namespace
+
+size_t network_lds_bytes(const Mlp& m) { return m.bytes16 + sizeof(float) * (size_t)m.L * 16 * m.mb; }
+
+namespace {
+
+hipError_t prepare_fused(const void* fn) {
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, fn);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(kMlpLdsBytes - attr.sharedSizeBytes));
+}
+
+}  // namespace
+
+int blur_mlp_tile_rows(p2s_precision prec, int nmb) {
+    return prec == P2S_FP8E4M3 ? 8 : 2 * fused_nblk_bf16(nmb);
+}
+
+bool blur_mlp_supported(const Basis& b, const Mlp& m, p2s_precision prec) {
+    return fused_fn(b, m, prec, false) != nullptr && fused_fn(b, m, prec, true) != nullptr;
+}
+
+int blur_mlp_batch_resident(const Basis& b, const Mlp& m, p2s_precision prec) {
+    const void* fn = fused_fn(b, m, prec, true);
+    if (!fn || prepare_fused(fn) != hipSuccess) return 0;
+    return resident_workgroups(fn, 256, network_lds_bytes(m));
+}
+
+hipError_t launch_blur_mlp(const Basis& b, const Mlp& m, p2s_precision prec, const float* img, int C, int H, int W,
+                           const float* fields, float* out, hipStream_t s) {
+    const void* fn = fused_fn(b, m, prec, false);
+    if (!fn) return hipErrorInvalidValue;
+    hipError_t e = prepare_fused(fn);
+    if (e != hipSuccess) return e;
+    MlpArgs a{};
+    a.L = m.L;
+    a.n_in = m.dims[0];
+    a.K = m.dims[m.L];
+    for (int l = 0; l < m.L; ++l) a.boff[l] = m.boff[l];
+    fill_weight_args(m, P2S_BF16, a);
+    const int TY = blur_mlp_tile_rows(prec, b.nmb);
+    int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + TY - 1) / TY;
+    const int items = tiles_x * tiles_y * C;
+    const int grid = std::min(items, resident_workgroups(fn, 256, network_lds_bytes(m)));
+    const uint4* bp = reinterpret_cast<const uint4*>(prec == P2S_BF16 ? (const void*)b.bf16 : (const void*)b.fp8);
+    const int* scale = b.fp8_scale;
+    const uint4* wg16 = reinterpret_cast<const uint4*>(m.w16);
+    const float* bias = m.bias;
+    const float* fields2 = fields + 2 * (size_t)H * W;
+    void* args[] = {&img, &C, &H, &W, &bp, &scale, &a, &wg16, &bias, &fields2, &out, &tiles_x, &tiles_y};
+    return hipLaunchKernel(fn, dim3(grid), dim3(256), args, network_lds_bytes(m), s);
+}
+
+hipError_t launch_blur_mlp_batch(const Basis& b, const Mlp& m, const BatchLaunch& bl, p2s_precision prec,
+                                 hipStream_t s) {
+    if (bl.items[ST_BLUR] == 0) return hipSuccess;
+    const void* fn = fused_fn(b, m, prec, true);
+    if (!fn) return hipErrorInvalidValue;
+    hipError_t e = prepare_fused(fn);
+    if (e != hipSuccess) return e;
+    MlpArgs a{};
+    a.L = m.L;
+    a.n_in = m.dims[0];
+    a.K = m.dims[m.L];
+    for (int l = 0; l < m.L; ++l) a.boff[l] = m.boff[l];
+    fill_weight_args(m, P2S_BF16, a);
+    const FrameDesc* fr = bl.frames;
+    const int* first = bl.first + ST_BLUR * (bl.n + 1);
+    int n = bl.n;
+    const uint4* bp = reinterpret_cast<const uint4*>(prec == P2S_BF16 ? (const void*)b.bf16 : (const void*)b.fp8);
+    const int* scale = b.fp8_scale;
+    const uint4* wg16 = reinterpret_cast<const uint4*>(m.w16);
+    const float* bias = m.bias;
+    void* args[] = {&fr, &first, &n, &bp, &scale, &a, &wg16, &bias};
+    return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(256), args, network_lds_bytes(m), s);
 }
 
 hipError_t launch_blur(const Basis& b, const float* img, int C, int H, int W, const float* w, p2s_precision prec,

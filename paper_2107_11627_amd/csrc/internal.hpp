@@ -15,6 +15,7 @@ namespace p2s {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
+typedef float floatx8 __attribute__((ext_vector_type(8)));
 
 // Device copy of a PSF basis, laid out as MFMA A-operands (rows = basis
 // functions in blocks of 16, reduction = PSF taps).  Taps are stored in
@@ -162,6 +163,16 @@ hipError_t launch_blur(const Basis& b, const float* img, int C, int H, int W, co
                        p2s_precision prec, float* out, hipStream_t s);
 hipError_t launch_warp(const float* in, int C, int H, int W, const float* tilt, double scale,
                        float* out, hipStream_t s);
+// Network fused into the blur (BF16 network, BF16 or FP8 blur); `fields` is
+// the frame's full [nz][H][W] array.
+bool blur_mlp_supported(const Basis& b, const Mlp& m, p2s_precision prec);
+size_t network_lds_bytes(const Mlp& m);               // packed BF16 weights + biases
+int blur_mlp_tile_rows(p2s_precision prec, int nmb);   // output rows per fused work item
+int blur_mlp_batch_resident(const Basis& b, const Mlp& m, p2s_precision prec);
+hipError_t launch_blur_mlp(const Basis& b, const Mlp& m, p2s_precision prec, const float* img, int C, int H, int W,
+                           const float* fields, float* out, hipStream_t s);
+hipError_t launch_blur_mlp_batch(const Basis& b, const Mlp& m, const BatchLaunch& bl, p2s_precision prec,
+                                 hipStream_t s);
 
 // --------------------------------------------------------- host helpers
 uint16_t f32_to_bf16_rne(float x);
@@ -175,5 +186,10 @@ __device__ __forceinline__ uint32_t bf16_bits_rne(float x) {
     return u >> 16;
 }
 __device__ __forceinline__ float bf16_bits_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+// Eight float32 values to bfloat16, round to nearest even (one conversion
+// instruction per pair on gfx950); bit-identical to bf16_bits_rne for finite
+// values.
+__device__ __forceinline__ bf16x8 to_bf16x8(floatx8 v) { return __builtin_convertvector(v, bf16x8); }
+__device__ __forceinline__ floatx8 from_bf16x8(bf16x8 v) { return __builtin_convertvector(v, floatx8); }
 
 }  // namespace p2s

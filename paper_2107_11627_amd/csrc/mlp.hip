@@ -19,7 +19,7 @@
 // and FP32 accumulation, so only the weights are rounded.
 #include <algorithm>
 
-#include "internal.hpp"
+#include "mlp_block.hpp"
 
 namespace p2s {
 namespace {
@@ -27,36 +27,6 @@ namespace {
 constexpr int kWaves = 8;
 constexpr int kNb = 2;                       // pixel blocks of 16 per wave
 constexpr int kPixPerGroup = kWaves * kNb * 16;
-
-struct MlpArgs {
-    int L;
-    int n_in;
-    int nkc0;                       // layer-0 reduction chunks
-    int woff[P2S_MAX_LAYERS];       // element offsets into the packed weights
-    int boff[P2S_MAX_LAYERS];
-    int HW;
-    int K;
-    int ngroups;
-    int wtotal;                     // packed weight elements (floats, or uint4 for BF16)
-};
-
-template <typename T>
-__device__ void stage_weights(T* lds, const T* __restrict__ g, int n) {
-    constexpr int kB = 8;
-    for (int base = 0; base < n; base += kB * (int)blockDim.x) {
-        T v[kB];
-#pragma unroll
-        for (int i = 0; i < kB; ++i) {
-            const int idx = base + i * (int)blockDim.x + (int)threadIdx.x;
-            v[i] = g[idx < n ? idx : 0];
-        }
-#pragma unroll
-        for (int i = 0; i < kB; ++i) {
-            const int idx = base + i * (int)blockDim.x + (int)threadIdx.x;
-            if (idx < n) lds[idx] = v[i];
-        }
-    }
-}
 
 // bias, ReLU (hidden layers) and the move into the next layer's inputs
 template <int MB>
@@ -190,144 +160,18 @@ __global__ void __launch_bounds__(kWaves * 64) mlp_f32_batch(MlpArgs a, const Fr
 }
 
 // ------------------------------------------------------------------ BF16
-__device__ __forceinline__ void split8(const float v[8], bf16x8& hi, bf16x8& lo) {
-    uint32_t h[8], l[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        h[e] = bf16_bits_rne(v[e]);
-        l[e] = bf16_bits_rne(v[e] - bf16_bits_to_f32(h[e]));
-    }
-    uint4 ph = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
-    uint4 pl = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), l[6] | (l[7] << 16));
-    hi = __builtin_bit_cast(bf16x8, ph);
-    lo = __builtin_bit_cast(bf16x8, pl);
-}
-
 template <int MB>
-__device__ __forceinline__ void mlp_bf16_group(const MlpArgs& a, const uint4* __restrict__ lds_w16, const float* __restrict__ bias,
-                               const float* __restrict__ fields, float* __restrict__ wout, int HW, int grp) {
+__device__ __forceinline__ void mlp_bf16_group(const MlpArgs& a, const uint4* __restrict__ lds_w16,
+                                               const float* __restrict__ bias, const float* __restrict__ fields,
+                                               float* __restrict__ wout, int HW, int grp) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, m = lane & 15;
-    constexpr int MBE = (MB + 1) & ~1;      // even block count: chunks pair blocks
-    constexpr int NKC = MBE / 2;
     const int pix0 = grp * kPixPerGroup + wave * kNb * 16;
     int pixc[kNb];
 #pragma unroll
     for (int nb = 0; nb < kNb; ++nb) pixc[nb] = min(pix0 + nb * 16 + m, HW - 1);
-    float act[kNb][MBE][4];
-    floatx4 acc[kNb][MB];
-    // layer 0: chunk kc covers features 32 kc + 8 g + e
-    {
-        bf16x8 xh[kNb][2], xl[kNb][2];
-#pragma unroll
-        for (int kc = 0; kc < 2; ++kc) {
-            float v[kNb][8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int f = 32 * kc + 8 * g + e;
-                const int fc = min(f, a.n_in - 1);
-                const float fm = f < a.n_in ? 1.0f : 0.0f;
-#pragma unroll
-                for (int nb = 0; nb < kNb; ++nb) v[nb][e] = fields[(size_t)fc * HW + pixc[nb]] * fm;
-            }
-#pragma unroll
-            for (int nb = 0; nb < kNb; ++nb) split8(v[nb], xh[nb][kc], xl[nb][kc]);
-        }
-        const uint4* w0 = lds_w16 + a.woff[0];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            bf16x8 wa[2];
-#pragma unroll
-            for (int kc = 0; kc < 2; ++kc) wa[kc] = __builtin_bit_cast(bf16x8, w0[(mb * 2 + kc) * 64 + lane]);
-            floatx4 c[kNb];
-#pragma unroll
-            for (int nb = 0; nb < kNb; ++nb) c[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kc = 0; kc < 2; ++kc) {
-                if (kc < a.nkc0) {
-#pragma unroll
-                    for (int nb = 0; nb < kNb; ++nb) {
-                        c[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kc], xh[nb][kc], c[nb], 0, 0, 0);
-                        c[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kc], xl[nb][kc], c[nb], 0, 0, 0);
-                    }
-                }
-            }
-#pragma unroll
-            for (int nb = 0; nb < kNb; ++nb) acc[nb][mb] = c[nb];
-        }
-    }
-#pragma unroll
-    for (int nb = 0; nb < kNb; ++nb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) act[nb][MBE - 1][i] = 0.0f;   // padding block when MB is odd
-    {
-        // bias/ReLU into act[.][0..MB)
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float b = bias[a.boff[0] + 16 * mb + 4 * g + i];
-#pragma unroll
-                for (int nb = 0; nb < kNb; ++nb) {
-                    const float v = acc[nb][mb][i] + b;
-                    act[nb][mb][i] = (a.L == 1) ? v : fmaxf(v, 0.0f);
-                }
-            }
-    }
-    for (int l = 1; l < a.L; ++l) {
-        bf16x8 xh[kNb][NKC], xl[kNb][NKC];
-#pragma unroll
-        for (int nb = 0; nb < kNb; ++nb)
-#pragma unroll
-            for (int kc = 0; kc < NKC; ++kc) {
-                float v[8];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    v[e] = act[nb][2 * kc][e];
-                    v[4 + e] = act[nb][2 * kc + 1][e];
-                }
-                split8(v, xh[nb][kc], xl[nb][kc]);
-            }
-        const uint4* wl = lds_w16 + a.woff[l];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            bf16x8 wa[NKC];
-#pragma unroll
-            for (int kc = 0; kc < NKC; ++kc) wa[kc] = __builtin_bit_cast(bf16x8, wl[(mb * NKC + kc) * 64 + lane]);
-            floatx4 c[kNb];
-#pragma unroll
-            for (int nb = 0; nb < kNb; ++nb) c[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kc = 0; kc < NKC; ++kc)
-#pragma unroll
-                for (int nb = 0; nb < kNb; ++nb) {
-                    c[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kc], xh[nb][kc], c[nb], 0, 0, 0);
-                    c[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kc], xl[nb][kc], c[nb], 0, 0, 0);
-                }
-#pragma unroll
-            for (int nb = 0; nb < kNb; ++nb) acc[nb][mb] = c[nb];
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        const bool last = (l == a.L - 1);
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float b = bias[a.boff[l] + 16 * mb + 4 * g + i];
-#pragma unroll
-                for (int nb = 0; nb < kNb; ++nb) {
-                    const float v = acc[nb][mb][i] + b;
-                    act[nb][mb][i] = last ? v : fmaxf(v, 0.0f);
-                }
-            }
-    }
     float outv[kNb][MB][4];
-#pragma unroll
-    for (int nb = 0; nb < kNb; ++nb)
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) outv[nb][mb][i] = act[nb][mb][i];
+    mlp_bf16_blocks<MB, kNb>(a, lds_w16, bias, fields, HW, pixc, outv);
     store_w<MB>(outv, wout, pix0, m, g, HW, a.K);
 }
 
@@ -337,10 +181,10 @@ __global__ void __launch_bounds__(kWaves * 64) mlp_bf16_kernel(MlpArgs a, const 
                                                                const float* __restrict__ bias,
                                                                float* __restrict__ wout) {
     extern __shared__ uint4 lds_w16[];
-    stage_weights(lds_w16, wg, a.wtotal);
+    const float* lds_bias = stage_bf16_network(lds_w16, a, wg, bias);
     __syncthreads();
     for (int grp = blockIdx.x; grp < a.ngroups; grp += gridDim.x)
-        mlp_bf16_group<MB>(a, lds_w16, bias, fields, wout, a.HW, grp);
+        mlp_bf16_group<MB>(a, lds_w16, lds_bias, fields, wout, a.HW, grp);
 }
 
 template <int MB>
@@ -349,13 +193,13 @@ __global__ void __launch_bounds__(kWaves * 64) mlp_bf16_batch(MlpArgs a, const F
                                                               const uint4* __restrict__ wg,
                                                               const float* __restrict__ bias) {
     extern __shared__ uint4 lds_w16[];
-    stage_weights(lds_w16, wg, a.wtotal);
+    const float* lds_bias = stage_bf16_network(lds_w16, a, wg, bias);
     __syncthreads();
     const int total = first[n];
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int f = find_frame(first, n, item);
         const int HW = fr[f].H * fr[f].W;
-        mlp_bf16_group<MB>(a, lds_w16, bias, fr[f].fields + 2 * (size_t)HW, fr[f].w, HW, item - first[f]);
+        mlp_bf16_group<MB>(a, lds_w16, lds_bias, fr[f].fields + 2 * (size_t)HW, fr[f].w, HW, item - first[f]);
     }
 }
 
@@ -375,6 +219,8 @@ hipError_t set_attrs() {
     return hipSuccess;
 }
 
+}  // namespace
+
 void fill_weight_args(const Mlp& mm, p2s_precision prec, MlpArgs& a) {
     if (prec == P2S_FP32) {
         for (int l = 0; l < mm.L; ++l) a.woff[l] = (int)(mm.off32[l] / sizeof(float));
@@ -385,7 +231,10 @@ void fill_weight_args(const Mlp& mm, p2s_precision prec, MlpArgs& a) {
         a.nkc0 = mm.nkc16[0];
         a.wtotal = (int)(mm.bytes16 / 16);
     }
+    a.nbias = mm.L * 16 * mm.mb;
 }
+
+namespace {
 
 template <int MB>
 hipError_t launch_mb_batch(const Mlp& mm, const MlpArgs& a0, const BatchLaunch& bl, p2s_precision prec,
@@ -399,7 +248,8 @@ hipError_t launch_mb_batch(const Mlp& mm, const MlpArgs& a0, const BatchLaunch& 
         hipLaunchKernelGGL(mlp_f32_batch<MB>, dim3(bl.grid[ST_MLP]), dim3(kWaves * 64), mm.bytes32, s, a, bl.frames,
                            first, bl.n, mm.w32, mm.bias);
     else
-        hipLaunchKernelGGL(mlp_bf16_batch<MB>, dim3(bl.grid[ST_MLP]), dim3(kWaves * 64), mm.bytes16, s, a, bl.frames,
+        hipLaunchKernelGGL(mlp_bf16_batch<MB>, dim3(bl.grid[ST_MLP]), dim3(kWaves * 64),
+                           mm.bytes16 + 4 * (size_t)a.nbias, s, a, bl.frames,
                            first, bl.n, reinterpret_cast<const uint4*>(mm.w16), mm.bias);
     return hipGetLastError();
 }
@@ -418,11 +268,9 @@ hipError_t launch_mb(const Mlp& mm, const MlpArgs& a0, const float* fields, p2s_
         hipLaunchKernelGGL(mlp_f32_kernel<MB>, dim3(grid), dim3(kWaves * 64), mm.bytes32, s, a, fields, mm.w32,
                            mm.bias, w);
     } else {
-        for (int l = 0; l < mm.L; ++l) a.woff[l] = (int)(mm.off16[l] / 16);
-        a.nkc0 = mm.nkc16[0];
-        a.wtotal = (int)(mm.bytes16 / 16);
-        hipLaunchKernelGGL(mlp_bf16_kernel<MB>, dim3(grid), dim3(kWaves * 64), mm.bytes16, s, a, fields,
-                           reinterpret_cast<const uint4*>(mm.w16), mm.bias, w);
+        fill_weight_args(mm, prec, a);
+        hipLaunchKernelGGL(mlp_bf16_kernel<MB>, dim3(grid), dim3(kWaves * 64), mm.bytes16 + 4 * (size_t)a.nbias, s,
+                           a, fields, reinterpret_cast<const uint4*>(mm.w16), mm.bias, w);
     }
     return hipGetLastError();
 }

@@ -25,7 +25,7 @@ EXPORTS = [
     "p2s_version", "p2s_last_error", "p2s_noll_variance", "p2s_field_grid",
     "p2s_fields_workspace_bytes", "p2s_workspace_bytes", "p2s_basis_create",
     "p2s_basis_destroy", "p2s_basis_info", "p2s_mlp_create", "p2s_mlp_destroy",
-    "p2s_mlp_info", "p2s_make_fields", "p2s_mlp", "p2s_blur", "p2s_warp",
+    "p2s_mlp_info", "p2s_make_fields", "p2s_mlp", "p2s_blur", "p2s_mlp_blur", "p2s_warp",
     "p2s_simulate", "p2s_debug_noise", "p2s_batch_workspace_bytes", "p2s_batch_create",
     "p2s_batch_upload", "p2s_batch_launch", "p2s_batch_info", "p2s_batch_destroy", "p2s_simulate_batch",
 ]
@@ -82,6 +82,7 @@ def lib():
         L.p2s_make_fields.argtypes = [i, i, d, i, u64, vp, vp, vp, sz, vp]
         L.p2s_mlp.argtypes = [vp, vp, i, i, i, i, vp, vp]
         L.p2s_blur.argtypes = [vp, i, i, i, vp, vp, i, vp, vp]
+        L.p2s_mlp_blur.argtypes = [vp, vp, i, vp, i, i, i, vp, i, vp, vp]
         L.p2s_warp.argtypes = [vp, i, i, i, vp, vp, vp, vp]
         L.p2s_simulate.argtypes = [vp, i, i, i, d, i, vp, vp, u64, i, vp, vp, vp, sz, vp]
         L.p2s_debug_noise.argtypes = [i, i, i, u64, vp, vp, vp]
@@ -242,6 +243,15 @@ def blur(image, basis: Basis, w, precision, out, stream=None):
     _check(lib().p2s_blur(_ptr(image, torch.float32, None, "image"), C_, H, W, basis.handle,
                           _ptr(w, torch.float32, (H * W, basis.K), "w"), _prec(precision),
                           _ptr(out, torch.float32, (C_, H, W), "out"), _stream(stream)))
+
+
+def mlp_blur(net: Mlp, fields, n_zernike, image, basis: Basis, precision, out, stream=None):
+    """Network and blur in one kernel (BF16 network; BF16 or FP8 blur)."""
+    import torch
+    C_, H, W = image.shape
+    _check(lib().p2s_mlp_blur(net.handle, _ptr(fields, torch.float32, (n_zernike, H, W), "fields"), n_zernike,
+                              _ptr(image, torch.float32, None, "image"), C_, H, W, basis.handle, _prec(precision),
+                              _ptr(out, torch.float32, (C_, H, W), "out"), _stream(stream)))
 
 
 def warp(inp, tilt, out, q_sampling=2.0, stream=None):

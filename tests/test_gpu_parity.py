@@ -243,6 +243,70 @@ def test_warp_zero_tilt_is_identity(p2s):
     assert np.array_equal(host(out), img)
 
 
+# ------------------------------------------------------- fused network+blur
+@pytest.mark.parametrize("dims,K,P,C,H,W,prec", [
+    ((33, 100, 100, 100), 100, 33, 1, 96, 80, "bf16"),
+    ((33, 100, 100, 100), 100, 33, 3, 37, 45, "bf16"),
+    ((33, 48, 48, 40), 40, 17, 2, 50, 70, "bf16"),
+    ((33, 48, 48, 40), 40, 17, 2, 50, 70, "fp8"),
+    ((33, 16, 16), 16, 9, 1, 33, 65, "fp8"),
+])
+def test_mlp_blur_fused_equals_staged(p2s, dims, K, P, C, H, W, prec):
+    """The network evaluated inside the blur epilogue gives bit for bit what
+    p2s_mlp followed by p2s_blur gives (same MFMA arithmetic per pixel)."""
+    Ws, bs = S.xavier_mlp(dims, 31, bias_scale=0.05)
+    net = p2s.Mlp(Ws, bs)
+    basis = p2s.Basis(np.random.default_rng(K + P).normal(size=(K, P, P)) / P)
+    nz = dims[0] + 2
+    F = dev(synthetic_fields(nz, H, W, 5))
+    img = dev(np.random.default_rng(6).random((C, H, W)))
+    w = torch.empty((H * W, K), dtype=torch.float32, device="cuda")
+    staged = torch.empty((C, H, W), dtype=torch.float32, device="cuda")
+    fused = torch.full((C, H, W), -1.0, dtype=torch.float32, device="cuda")
+    p2s.mlp(net, F, nz, H, W, prec, w)
+    p2s.blur(img, basis, w, prec, staged)
+    p2s.mlp_blur(net, F, nz, img, basis, prec, fused)
+    assert np.array_equal(host(fused), host(staged))
+
+
+def test_mlp_blur_unsupported(p2s):
+    wl = S.workload("single128")
+    Ws, bs = wl.mlp()                        # 33-64-64-16: hidden layers wider than the K = 16 basis
+    net = p2s.Mlp(Ws, bs)
+    basis = p2s.Basis(np.random.default_rng(1).normal(size=(16, 17, 17)))
+    F = torch.zeros((35, 8, 8), device="cuda")
+    img = torch.zeros((1, 8, 8), device="cuda")
+    out = torch.empty_like(img)
+    for prec in ("bf16", "fp32"):
+        with pytest.raises(p2s.P2SError) as e:
+            p2s.mlp_blur(net, F, 35, img, basis, prec, out)
+        assert e.value.code == p2s.P2S_EUNSUPPORTED
+
+
+def test_simulate_fused_equals_staged(p2s):
+    """p2s_simulate (network fused into the blur for this workload) against
+    the four stage calls made one by one."""
+    wl = S.workload("single512")
+    f = wl.frames[0]
+    basis = oracle_basis("single512")
+    Ws, bs = wl.mlp()
+    sim = p2s.Simulator(basis, Ws, bs, n_zernike=35)
+    img = dev(f.image())
+    for prec in ("bf16", "fp8"):
+        got = host(sim(img, f.d_over_r0, f.field_seed, prec))
+        H, W = f.H, f.W
+        F = torch.empty((35, H, W), dtype=torch.float32, device="cuda")
+        fws = torch.empty(p2s.fields_workspace_bytes(H, W, 35), dtype=torch.uint8, device="cuda")
+        w = torch.empty((H * W, 100), dtype=torch.float32, device="cuda")
+        bl = torch.empty_like(img)
+        out = torch.empty_like(img)
+        p2s.make_fields(H, W, f.d_over_r0, 35, f.field_seed, F, fws)
+        p2s.mlp(sim.net, F, 35, H, W, prec, w)
+        p2s.blur(img, sim.basis, w, prec, bl)
+        p2s.warp(bl, F, out)
+        assert np.array_equal(got, host(out)), prec
+
+
 # --------------------------------------------------------------- simulate
 def run_sim(p2s, img, d, basis, Ws, bs, seed, prec, nz=35):
     C, H, W = img.shape
