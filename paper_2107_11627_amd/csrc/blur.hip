@@ -764,13 +764,13 @@ namespace {
 // (4 NBLK NMB registers) and the network's live values must share the wave's
 // 256 accumulation-capable registers, so wide bases take 12-row or 8-row tiles.
 constexpr int fused_nblk_bf16(int nmb) { return nmb >= 8 ? 2 : (nmb >= 5 ? 4 : 8); }
+constexpr int fused_nblk_fp8(int nmb) { return nmb >= 7 ? 2 : 4; }
 
 template <int P, int NMB>
 const void* fused_fn_nmb(p2s_precision prec, bool batch) {
     if (prec == P2S_FP8E4M3) {
-        if constexpr (NMB <= 4)
-            return batch ? (const void*)blur_mlp_batch<P, NMB, 4, true> : (const void*)blur_mlp_kernel<P, NMB, 4, true>;
-        return nullptr;
+        constexpr int NBLK = fused_nblk_fp8(NMB);
+        return batch ? (const void*)blur_mlp_batch<P, NMB, NBLK, true> : (const void*)blur_mlp_kernel<P, NMB, NBLK, true>;
     }
     constexpr int NBLK = fused_nblk_bf16(NMB);
     return batch ? (const void*)blur_mlp_batch<P, NMB, NBLK, false> : (const void*)blur_mlp_kernel<P, NMB, NBLK, false>;
@@ -829,7 +829,7 @@ hipError_t prepare_fused(const void* fn) {
 }  // namespace
 
 int blur_mlp_tile_rows(p2s_precision prec, int nmb) {
-    return prec == P2S_FP8E4M3 ? 8 : 2 * fused_nblk_bf16(nmb);
+    return 2 * (prec == P2S_FP8E4M3 ? fused_nblk_fp8(nmb) : fused_nblk_bf16(nmb));
 }
 
 bool blur_mlp_supported(const Basis& b, const Mlp& m, p2s_precision prec) {
