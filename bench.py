@@ -12,8 +12,10 @@ Printed: ONE JSON line on stdout (progress goes to stderr) with
   fp32         the same for the plain FP32 path
   fp8          the same with the blur on FP8 E4M3 MFMA (network BF16)
   latency      p50/p99 single-frame latency, each frame synchronised
-  stages_us    per-stage device time (events around each ABI call)
-  roofline     dominant kernel (BF16 fused blur) against the BF16 MFMA peak
+  stages_us    per-stage device time (events around each ABI call); mlp_blur
+               is the kernel the frame runs (network inside the blur)
+  roofline     dominant kernel (network + blur, BF16) against the BF16 MFMA
+               peak, with the w-reading blur kernel alone beside it
   cpu_baseline the FP64 oracle timed on this host on a bounded sample, with
                the GPU outputs' relative L2 error against it
 """
@@ -45,6 +47,11 @@ def blur_flops(C, H, W, K, P):
     return 2.0 * C * H * W * K * (P * P + 1)
 
 
+def mlp_flops(H, W, dims):
+    """Algorithmic flops of the P2S network at every pixel: 2 in out per layer."""
+    return 2.0 * H * W * sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1))
+
+
 def src_digest(*paths):
     h = hashlib.sha256()
     for p in paths:
@@ -57,7 +64,7 @@ def traffic_from_profiles(kernel_sources):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, only if the kernel sources still match the digest recorded with
     the counters; else None."""
-    path = os.path.join(ROOT, "profiles", "blur_bf16_single512_traffic.json")
+    path = os.path.join(ROOT, "profiles", "blur_mlp_bf16_single512_traffic.json")
     if not os.path.exists(path):
         return None
     try:
@@ -87,6 +94,29 @@ def copy_mode(args, torch):
     us = e0.elapsed_time(e1) * 1e3 / args.steps
     print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
                       "avg_us": us, "GBps": 8 * n / us / 1e3}), flush=True)
+
+
+def mlp_blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C, dims):
+    """Only the kernel the frame spends most time in (network inside the
+    blur), args.steps launches on one frame's fields."""
+    F = torch.empty((NZ, H, W), dtype=torch.float32, device="cuda")
+    fws = torch.empty(p2s.fields_workspace_bytes(H, W, NZ), dtype=torch.uint8, device="cuda")
+    bl = torch.empty_like(img)
+    p2s.make_fields(H, W, fr.d_over_r0, NZ, fr.field_seed, F, fws)
+    for _ in range(args.warmup):
+        p2s.mlp_blur(sim.net, F, NZ, img, sim.basis, args.precision, bl)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        p2s.mlp_blur(sim.net, F, NZ, img, sim.basis, args.precision, bl)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / args.steps
+    fl = blur_flops(C, H, W, K, P) + mlp_flops(H, W, dims)
+    print(json.dumps({"mode": "mlp_blur", "precision": args.precision, "avg_us": us,
+                      "TFLOPs": fl / us / 1e6, "algorithmic_flops_per_launch": fl,
+                      "algorithmic_bytes_per_launch": 4 * (2 * C * H * W + (NZ - 2) * H * W)}), flush=True)
 
 
 def blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C):
@@ -277,8 +307,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-slots", type=int, default=2)
     ap.add_argument("--serving-max-batch", type=int, default=16)
-    ap.add_argument("--mode", choices=["frame", "blur", "copy"], default="frame",
-                    help="frame: the benchmark; blur: only the fused blur of the workload (for counter runs); "
+    ap.add_argument("--mode", choices=["frame", "blur", "mlp_blur", "copy"], default="frame",
+                    help="frame: the benchmark; blur / mlp_blur: only the blur kernel, or the network-and-blur "
+                         "kernel, of the workload (for counter runs); "
                          "copy: a plain device copy of known size (calibrates byte counters)")
     ap.add_argument("--precision", choices=["bf16", "fp32", "fp8"], default="bf16", help="precision of --mode blur")
     args = ap.parse_args()
@@ -318,6 +349,8 @@ def main():
 
     if args.mode == "blur":
         return blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C)
+    if args.mode == "mlp_blur":
+        return mlp_blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C, wl.mlp_dims)
 
     res = {}
     outs = {}
@@ -358,9 +391,10 @@ def main():
         wbuf = torch.empty((H * W, K), dtype=torch.float32, device="cuda")
         fws = torch.empty(p2s.fields_workspace_bytes(H, W, NZ), dtype=torch.uint8, device="cuda")
         bl = torch.empty_like(img)
-        stages = {"fields": [], "mlp": [], "blur": [], "warp": []}
+        fused = prec != "fp32"
+        stages = {"fields": [], "mlp": [], "blur": [], "mlp_blur": [], "warp": []}
         for r in range(args.stage_reps + 2):
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
             ev[0].record(stream)
             p2s.make_fields(H, W, fr.d_over_r0, NZ, 1000 + r, F, fws)
             ev[1].record(stream)
@@ -368,12 +402,17 @@ def main():
             ev[2].record(stream)
             p2s.blur(img, sim.basis, wbuf, prec, bl)
             ev[3].record(stream)
-            p2s.warp(bl, F, out)
+            if fused:                        # network and blur in one kernel, as the frame runs them
+                p2s.mlp_blur(sim.net, F, NZ, img, sim.basis, prec, bl)
             ev[4].record(stream)
+            p2s.warp(bl, F, out)
+            ev[5].record(stream)
             torch.cuda.synchronize()
             if r >= 2:
                 for k, name in enumerate(stages):
                     stages[name].append(ev[k].elapsed_time(ev[k + 1]) * 1e3)
+        if not fused:
+            del stages["mlp_blur"]
         res[prec]["stages_us"] = {k: float(np.mean(v)) for k, v in stages.items()}
         log(f"[bench] {prec} stages (us): " + ", ".join(f"{k} {v:.1f}" for k, v in res[prec]["stages_us"].items()))
         del wbuf, fws, bl
@@ -383,19 +422,28 @@ def main():
         outs[prec] = out.cpu().numpy().astype(np.float64)
 
     flops = blur_flops(C, H, W, K, P)
+    nflops = mlp_flops(H, W, wl.mlp_dims)
+    fused_s = res["bf16"]["stages_us"]["mlp_blur"] * 1e-6
+    achieved = (flops + nflops) / fused_s / 1e12
+    kernel_src = ["paper_2107_11627_amd/csrc/blur.hip", "paper_2107_11627_amd/csrc/mlp_block.hpp",
+                  "paper_2107_11627_amd/csrc/internal.hpp"]
     blur_s = res["bf16"]["stages_us"]["blur"] * 1e-6
-    achieved = flops / blur_s / 1e12
-    kernel_src = ["paper_2107_11627_amd/csrc/blur.hip", "paper_2107_11627_amd/csrc/internal.hpp"]
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic_from_profiles(kernel_src),
-                "kernel": "blur_bf16_kernel<33,7,8>", "algorithmic_flops_per_launch": flops,
-                "avg_launch_us": blur_s * 1e6, "src_digest": src_digest(*kernel_src)}
+                "kernel": "blur_mlp_kernel<33,7,4,bf16>: P2S network evaluated inside the fused basis blur",
+                "algorithmic_flops_per_launch": flops + nflops,
+                "algorithmic_flops_split": {"blur": flops, "network": nflops},
+                "avg_launch_us": fused_s * 1e6, "src_digest": src_digest(*kernel_src),
+                "blur_only": {"kernel": "blur_bf16_kernel<33,7,8> (w read from memory)", "avg_launch_us": blur_s * 1e6,
+                              "achieved": flops / blur_s / 1e12, "frac": flops / blur_s / 1e12 / PEAK_BF16_TFLOPS}}
     fp32_blur_s = res["fp32"]["stages_us"]["blur"] * 1e-6
     fp32_roof = {"bound": "mfma", "achieved": flops / fp32_blur_s / 1e12, "peak": PEAK_FP32_TFLOPS,
                  "frac": flops / fp32_blur_s / 1e12 / PEAK_FP32_TFLOPS}
-    fp8_blur_s = res["fp8"]["stages_us"]["blur"] * 1e-6
-    fp8_roof = {"bound": "mfma", "achieved": flops / fp8_blur_s / 1e12, "peak": PEAK_FP8_TFLOPS,
-                "frac": flops / fp8_blur_s / 1e12 / PEAK_FP8_TFLOPS}
+    fp8_s = res["fp8"]["stages_us"]["mlp_blur"] * 1e-6
+    fp8_roof = {"bound": "mfma", "kernel": "blur_mlp_kernel<33,7,2,fp8> (FP8 blur, BF16 network)",
+                "achieved": (flops + nflops) / fp8_s / 1e12,
+                "peak": PEAK_FP8_TFLOPS, "frac": (flops + nflops) / fp8_s / 1e12 / PEAK_FP8_TFLOPS,
+                "note": "the network's share runs on BF16 MFMA (peak 2500)"}
 
     batches, batch_samples = (None, {}) if args.no_batches else batch_section(args, torch, p2s, S, pbasis)
     serving = None if args.no_serving else serving_section(args, torch, p2s, S, pbasis)
