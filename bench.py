@@ -96,6 +96,24 @@ def copy_mode(args, torch):
                       "avg_us": us, "GBps": 8 * n / us / 1e3}), flush=True)
 
 
+def fields_mode(args, torch, p2s, fr, NZ, H, W):
+    """Only the field generator of the workload, args.steps calls."""
+    F = torch.empty((NZ, H, W), dtype=torch.float32, device="cuda")
+    fws = torch.empty(p2s.fields_workspace_bytes(H, W, NZ), dtype=torch.uint8, device="cuda")
+    for i in range(args.warmup):
+        p2s.make_fields(H, W, fr.d_over_r0, NZ, 1000 + i, F, fws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(args.steps):
+        p2s.make_fields(H, W, fr.d_over_r0, NZ, 2000 + i, F, fws)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / args.steps
+    print(json.dumps({"mode": "fields", "avg_us": us, "output_bytes": 4 * NZ * H * W,
+                      "GBps_output": 4 * NZ * H * W / us / 1e3}), flush=True)
+
+
 def mlp_blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C, dims):
     """Only the kernel the frame spends most time in (network inside the
     blur), args.steps launches on one frame's fields."""
@@ -307,7 +325,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-slots", type=int, default=2)
     ap.add_argument("--serving-max-batch", type=int, default=16)
-    ap.add_argument("--mode", choices=["frame", "blur", "mlp_blur", "copy"], default="frame",
+    ap.add_argument("--mode", choices=["frame", "blur", "mlp_blur", "fields", "copy"], default="frame",
                     help="frame: the benchmark; blur / mlp_blur: only the blur kernel, or the network-and-blur "
                          "kernel, of the workload (for counter runs); "
                          "copy: a plain device copy of known size (calibrates byte counters)")
@@ -349,6 +367,8 @@ def main():
 
     if args.mode == "blur":
         return blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C)
+    if args.mode == "fields":
+        return fields_mode(args, torch, p2s, fr, NZ, H, W)
     if args.mode == "mlp_blur":
         return mlp_blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C, wl.mlp_dims)
 

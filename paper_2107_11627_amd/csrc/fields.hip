@@ -18,6 +18,8 @@
 //            FFT along x -> planes 2q, 2q+1 for x < W
 // FFTs: Stockham auto-sort in LDS, radix 4/2/3/5 passes, FP64-evaluated
 // twiddle table, thread -> (transform, butterfly) mapping by shifts.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace p2s {
@@ -192,7 +194,7 @@ __device__ __forceinline__ int ld_of(int N) { return N | 1; }   // odd stride sp
 // spectrum of those columns -> inverse FFT along y -> V.  Item (q=0, j0=0)
 // also publishes the row transforms' twiddle table.
 __device__ __forceinline__ void fields_cols_item(const FieldPlan& fp, float2* __restrict__ V, float2* __restrict__ twx_out,
-                                 int lg_cpb, int q, int j0, float2* smem) {
+                                 int lg_cpb, int q, int j0, float2* smem, bool fresh) {
     const int cpb = 1 << lg_cpb;
     const int N = fp.Nfy, ld = ld_of(N);
     float2* buf0 = smem;
@@ -206,8 +208,10 @@ __device__ __forceinline__ void fields_cols_item(const FieldPlan& fp, float2* __
             twx_out[k] = make_float2((float)cs, (float)sn);
         }
     }
-    fill_twiddles(tw, N);
-    for (int k = threadIdx.x; k < N; k += blockDim.x) filt[k] = gauss_filter(k, N, fp.corr_len);
+    if (fresh) {                               // first item of this frame in the workgroup
+        fill_twiddles(tw, N);
+        for (int k = threadIdx.x; k < N; k += blockDim.x) filt[k] = gauss_filter(k, N, fp.corr_len);
+    }
     __syncthreads();
     for (int idx = threadIdx.x; idx < cpb * N; idx += blockDim.x) {
         const int c = idx / N;                 // small: cpb <= 8
@@ -239,14 +243,15 @@ __device__ __forceinline__ void fields_cols_item(const FieldPlan& fp, float2* __
 // Row work item: plane pair q, output rows y0 .. y0 + 2^lg_rpb - 1.  V scattered
 // into the band bins -> inverse FFT along x -> planes 2q, 2q+1.
 __device__ __forceinline__ void fields_rows_item(const FieldPlan& fp, const float2* __restrict__ V, float* __restrict__ F,
-                                 const float2* __restrict__ twx, int lg_rpb, int q, int y0, float2* smem) {
+                                 const float2* __restrict__ twx, int lg_rpb, int q, int y0, float2* smem, bool fresh) {
     const int rpb = 1 << lg_rpb;
     const int N = fp.Nfx, ld = ld_of(N);
     float2* buf0 = smem;
     float2* buf1 = smem + rpb * ld;
     float2* tw = smem + 2 * rpb * ld;
     const int H = fp.H, W = fp.W, Mx = fp.Mx;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) tw[k] = twx[k];
+    if (fresh)                                 // first item of this frame in the workgroup
+        for (int k = threadIdx.x; k < N; k += blockDim.x) tw[k] = twx[k];
     for (int idx = threadIdx.x; idx < rpb * ld; idx += blockDim.x) buf0[idx] = make_float2(0.f, 0.f);
     __syncthreads();
     const float2* Vq = V + (size_t)q * H * Mx;
@@ -276,17 +281,27 @@ __device__ __forceinline__ void fields_rows_item(const FieldPlan& fp, const floa
     __syncthreads();                           // LDS free for the next item
 }
 
+// Single frame: persistent workgroups stride over the (pair, chunk) items, so
+// the twiddle table (and the column filter) is built once per workgroup.
 __global__ void __launch_bounds__(kThreads) fields_cols_kernel(FieldPlan fp, float2* __restrict__ V, int lg_cpb,
-                                                               float2* __restrict__ twx_out) {
+                                                               float2* __restrict__ twx_out, int nchunks) {
     extern __shared__ float2 smem[];
-    fields_cols_item(fp, V, twx_out, lg_cpb, blockIdx.y, blockIdx.x << lg_cpb, smem);
+    const int total = nchunks * fp.npairs;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int q = item / nchunks;
+        fields_cols_item(fp, V, twx_out, lg_cpb, q, (item - q * nchunks) << lg_cpb, smem, item == (int)blockIdx.x);
+    }
 }
 
 __global__ void __launch_bounds__(kThreads) fields_rows_kernel(FieldPlan fp, const float2* __restrict__ V,
                                                                float* __restrict__ F, int lg_rpb,
-                                                               const float2* __restrict__ twx) {
+                                                               const float2* __restrict__ twx, int nchunks) {
     extern __shared__ float2 smem[];
-    fields_rows_item(fp, V, F, twx, lg_rpb, blockIdx.y, blockIdx.x << lg_rpb, smem);
+    const int total = nchunks * fp.npairs;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int q = item / nchunks;
+        fields_rows_item(fp, V, F, twx, lg_rpb, q, (item - q * nchunks) << lg_rpb, smem, item == (int)blockIdx.x);
+    }
 }
 
 // Batched, persistent forms: workgroups stride over the (frame, item) list.
@@ -294,12 +309,14 @@ __global__ void __launch_bounds__(kThreads) fields_cols_batch(const FrameDesc* _
                                                               const int* __restrict__ first, int n) {
     extern __shared__ float2 smem[];
     const int total = first[n];
+    int prev = -1;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int f = find_frame(first, n, item);
         const FrameDesc& d = fr[f];
         const int l = item - first[f];
         const int q = l / d.ncol_chunks;
-        fields_cols_item(d.fp, d.V, d.twx, d.lg_cpb, q, (l - q * d.ncol_chunks) << d.lg_cpb, smem);
+        fields_cols_item(d.fp, d.V, d.twx, d.lg_cpb, q, (l - q * d.ncol_chunks) << d.lg_cpb, smem, f != prev);
+        prev = f;
     }
 }
 
@@ -307,12 +324,15 @@ __global__ void __launch_bounds__(kThreads) fields_rows_batch(const FrameDesc* _
                                                               const int* __restrict__ first, int n) {
     extern __shared__ float2 smem[];
     const int total = first[n];
+    int prev = -1;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int f = find_frame(first, n, item);
         const FrameDesc& d = fr[f];
         const int l = item - first[f];
         const int q = l / d.nrow_chunks;
-        fields_rows_item(d.fp, d.V, d.fields, d.twx, d.lg_rpb, q, (l - q * d.nrow_chunks) << d.lg_rpb, smem);
+        fields_rows_item(d.fp, d.V, d.fields, d.twx, d.lg_rpb, q, (l - q * d.nrow_chunks) << d.lg_rpb, smem,
+                         f != prev);
+        prev = f;
     }
 }
 
@@ -396,13 +416,23 @@ hipError_t launch_fields(const FieldPlan& fp, float* V, float* F, hipStream_t s)
     }
     float2* V2 = reinterpret_cast<float2*>(V);
     float2* twx = V2 + (size_t)fp.npairs * fp.H * fp.Mx;   // Nfx twiddles after the intermediate
-    dim3 gc((fp.Mx + (1 << lc) - 1) >> lc, fp.npairs);
-    hipLaunchKernelGGL(fields_cols_kernel, gc, dim3(kThreads), bc, s, fp, V2, lc, twx);
+    static int res_c = 0, res_r = 0;
+    static size_t res_c_lds = 0, res_r_lds = 0;
+    if (res_c_lds != bc) {
+        res_c = resident_workgroups((const void*)fields_cols_kernel, kThreads, bc);
+        res_c_lds = bc;
+    }
+    if (res_r_lds != br) {
+        res_r = resident_workgroups((const void*)fields_rows_kernel, kThreads, br);
+        res_r_lds = br;
+    }
+    const int nc = (fp.Mx + (1 << lc) - 1) >> lc, nr = (fp.H + (1 << lr) - 1) >> lr;
+    hipLaunchKernelGGL(fields_cols_kernel, dim3(std::min(nc * fp.npairs, res_c)), dim3(kThreads), bc, s, fp, V2, lc,
+                       twx, nc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 gr((fp.H + (1 << lr) - 1) >> lr, fp.npairs);
-    hipLaunchKernelGGL(fields_rows_kernel, gr, dim3(kThreads), br, s, fp, (const float2*)V2, F, lr,
-                       (const float2*)twx);
+    hipLaunchKernelGGL(fields_rows_kernel, dim3(std::min(nr * fp.npairs, res_r)), dim3(kThreads), br, s, fp,
+                       (const float2*)V2, F, lr, (const float2*)twx, nr);
     return hipGetLastError();
 }
 
