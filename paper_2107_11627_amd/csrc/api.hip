@@ -561,7 +561,8 @@ int batch_create(const p2s_frame* frames, int n, int nz, const Basis& B, const M
         lds_cols = std::max(lds_cols, fields_cols_lds(fp.Nfy, 1 << d.lg_cpb));
         lds_rows = std::max(lds_rows, fields_rows_lds(fp.Nfx, 1 << d.lg_rpb));
         const long long items[ST_N] = {(long long)fp.npairs * d.ncol_chunks, (long long)fp.npairs * d.nrow_chunks,
-                                       d.mlp_groups, (long long)f.C * d.tiles_x * d.tiles_y, d.warp_tiles};
+                                       d.mlp_groups, (long long)(fused ? 1 : f.C) * d.tiles_x * d.tiles_y,
+                                       d.warp_tiles};   // a fused item covers every channel of its tile
         for (int st = 0; st < ST_N; ++st) {
             tot[st] += items[st];
             if (tot[st] > std::numeric_limits<int>::max()) return fail(P2S_EINVAL, "batch too large");

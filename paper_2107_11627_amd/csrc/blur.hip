@@ -107,7 +107,7 @@ struct WFromMemory {
     }
 };
 
-template <int NMB, int NBLK>
+template <int NMB, int NBLK, bool EVAL>
 struct WFromNetwork {
     const MlpArgs* a;
     const uint4* lds_w16;
@@ -116,7 +116,7 @@ struct WFromNetwork {
     int H, W;
     float* out;
     float in[NBLK][2][8];             // the network inputs of the wave's pixel blocks
-    float wv[NBLK][NMB][4];           // the tile's weights, computed before the convolutions
+    float wv[NBLK][NMB][4];           // the tile's weights (EVAL: computed before the convolutions)
 
     __device__ __forceinline__ int pixel(int b, int yw, int x0, int m, bool& ok) const {
         const int y = yw + (b >> 1), x = x0 + (b & 1) * 16 + m;
@@ -127,6 +127,7 @@ struct WFromNetwork {
     // At the start of a tile: the field loads, in flight while the image is
     // staged.
     __device__ __forceinline__ void prefetch(int yw, int x0, int m) {
+        if constexpr (!EVAL) return;
         int pixc[NBLK];
         bool ok;
 #pragma unroll
@@ -135,9 +136,19 @@ struct WFromNetwork {
     }
 
     // Before the convolutions, while no accumulator is live: the network for
-    // all pixel blocks of the wave at once (every weight read from LDS serves
-    // all of them, and their MFMA chains interleave).
-    __device__ __forceinline__ void begin(int, int, int, int) { mlp_bf16_eval<NMB, NBLK>(*a, lds_w16, bias, in, wv); }
+    // the wave's pixel blocks, two at a time (every weight read from LDS
+    // serves both; more at once would need two full activation sets of
+    // registers for each).
+    __device__ __forceinline__ void begin(int, int, int, int) {
+        if constexpr (!EVAL) return;
+        constexpr int GB = NBLK >= 2 ? 2 : NBLK;
+#pragma unroll
+        for (int b0 = 0; b0 < NBLK; b0 += GB) {
+            const float (&ig)[GB][2][8] = *reinterpret_cast<const float (*)[GB][2][8]>(&in[b0]);
+            float (&og)[GB][NMB][4] = *reinterpret_cast<float (*)[GB][NMB][4]>(&wv[b0]);
+            mlp_bf16_eval<NMB, GB>(*a, lds_w16, bias, ig, og);
+        }
+    }
 
     __device__ __forceinline__ void operator()(const floatx4 (&acc)[NBLK][NMB], int yw, int x0, int g, int m,
                                                int c) const {
@@ -159,6 +170,15 @@ struct WFromNetwork {
         }
     }
 };
+
+// A tile buffer in LDS, one per (type, size, tag) and kernel: the fused
+// kernel instantiates a tile function twice (channel 0 with the network, the
+// other channels without), and both instances share these buffers.
+template <class T, int N, int TAG>
+__device__ __forceinline__ T* lds_buffer() {
+    __shared__ T buf[N];
+    return buf;
+}
 
 // Copy a clamped (replicate-border) window of image rows y_lo.. and columns
 // x_lo.. into LDS, nr x nc floats at pitch ld; loads are issued in batches of
@@ -279,9 +299,9 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
     constexpr int SW = kTX + 2 * R;              // fp32 staging tile
     constexpr int SH = (QH + 7 > PH ? QH + 7 : PH);
     static_assert(P == 8 * A8 + 1, "bf16 layout needs P = 8a + 1");
-    __shared__ uint4 rowpk[PH * PITCH];
-    __shared__ uint4 colpk[QH * CPITCH];
-    __shared__ float stage[SH * SW];
+    uint4* const rowpk = lds_buffer<uint4, PH * PITCH, 0>();
+    uint4* const colpk = lds_buffer<uint4, QH * CPITCH, 1>();
+    float* const stage = lds_buffer<float, SH * SW, 2>();
 
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x0 = tx * kTX, y0 = ty * TY;
@@ -311,10 +331,6 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
         }
         __syncthreads();
         floatx4 acc[NBLK][NMB];
-#pragma unroll
-        for (int b = 0; b < NBLK; ++b)
-#pragma unroll
-            for (int mb = 0; mb < NMB; ++mb) acc[b][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
         // B-operand source of chunk 4 t + g for this lane's pixel block 0, and
         // the row step of that kind of chunk
         auto chunk_src = [&](int t, int& step) -> const uint4* {
@@ -351,7 +367,11 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
                                                                         acc[b][mb], 0, 0, 0);
             }
         };
-        epi.begin(y0 + lyw, x0, g, m);
+        epi.begin(y0 + lyw, x0, g, m);           // before the accumulators are live
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) acc[b][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
         fetch(0, a0, p0);
 #pragma unroll 1
         for (int t = 0; t + 1 < T32; t += 2) {
@@ -402,9 +422,9 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
     constexpr int SW = kTX + 2 * R;
     constexpr int SH = (QH + 7 > PH ? QH + 7 : PH);
     static_assert(P == 8 * A8 + 1, "fp8 layout needs P = 8a + 1");
-    __shared__ uint2 rowpk8[NR * PITCH];
-    __shared__ uint2 colpk8[NR * PITCH];
-    __shared__ float stage8[SH * SW];
+    uint2* const rowpk8 = lds_buffer<uint2, NR * PITCH, 3>();
+    uint2* const colpk8 = lds_buffer<uint2, NR * PITCH, 4>();
+    float* const stage8 = lds_buffer<float, SH * SW, 5>();
 
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x0 = tx * kTX, y0 = ty * TY;
@@ -432,10 +452,6 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb) sc[mb] = scale[16 * mb + m];
     floatx4 acc[NBLK][NMB];
-#pragma unroll
-    for (int b = 0; b < NBLK; ++b)
-#pragma unroll
-        for (int mb = 0; mb < NMB; ++mb) acc[b][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int pbase = lyw * PITCH + m;
     auto chunk_src = [&](int ch) -> const uint2* {
         if (ch < NROW) {
@@ -484,7 +500,11 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
             __builtin_amdgcn_sched_barrier(0);
         }
     };
-    epi.begin(y0 + lyw, x0, g, m);
+    epi.begin(y0 + lyw, x0, g, m);               // before the accumulators are live
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb) acc[b][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
     load_a(0, a0);
 #pragma unroll 1
     for (int t = 0; t + 1 < T128; t += 2) {
@@ -568,17 +588,35 @@ __global__ void __launch_bounds__(256) blur_fp8_batch(const FrameDesc* __restric
 
 // Network fused into the blur (BF16 network; BF16 or FP8 blur): persistent
 // workgroups stage the packed network weights into dynamic LDS once, then
-// stride over (channel, tile) items of one frame, or over the (frame,
-// channel, tile) list of a batch.
+// stride over the tiles of one frame, or over the (frame, tile) list of a
+// batch.  An item blurs every channel of its tile with the weights the
+// network produced once for the tile's pixels.
 template <int P, int NMB, int NBLK, bool FP8>
-__device__ __forceinline__ void fused_item(const float* img, int H, int W, const uint4* bp, const int* scale,
+__device__ __forceinline__ void fused_item(const float* img, int C, int H, int W, const uint4* bp, const int* scale,
                                            const MlpArgs& a, const uint4* lds_w16, const float* bias,
-                                           const float* fields2, float* out, int tiles_x, int tile, int c) {
-    WFromNetwork<NMB, NBLK> epi{&a, lds_w16, bias, fields2, H, W, out, {}, {}};
+                                           const float* fields2, float* out, int tiles_x, int tile) {
+    // channel 0 runs the network; the other channels reuse its weights (a
+    // separate instance of the tile code, so that the network's registers
+    // are not held across the channel loop)
+    WFromNetwork<NMB, NBLK, true> first{&a, lds_w16, bias, fields2, H, W, out, {}, {}};
     if constexpr (FP8)
-        blur_fp8_tile<P, NMB, NBLK>(img, H, W, bp, scale, tiles_x, tile, c, epi);
+        blur_fp8_tile<P, NMB, NBLK>(img, H, W, bp, scale, tiles_x, tile, 0, first);
     else
-        blur_bf16_tile<P, NMB, NBLK>(img, H, W, bp, tiles_x, tile, c, epi);
+        blur_bf16_tile<P, NMB, NBLK>(img, H, W, bp, tiles_x, tile, 0, first);
+    if (C == 1) return;
+    WFromNetwork<NMB, NBLK, false> rest{&a, lds_w16, bias, fields2, H, W, out, {}, {}};
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) rest.wv[b][mb][i] = first.wv[b][mb][i];
+    for (int c = 1; c < C; ++c) {
+        if constexpr (FP8)
+            blur_fp8_tile<P, NMB, NBLK>(img, H, W, bp, scale, tiles_x, tile, c, rest);
+        else
+            blur_bf16_tile<P, NMB, NBLK>(img, H, W, bp, tiles_x, tile, c, rest);
+    }
 }
 
 template <int P, int NMB, int NBLK, bool FP8>
@@ -590,12 +628,9 @@ __global__ void __launch_bounds__(256) blur_mlp_kernel(const float* __restrict__
                                                        int tiles_x, int tiles_y) {
     extern __shared__ uint4 lds_w16[];
     const float* lds_bias = stage_bf16_network(lds_w16, a, wg16, bias);   // the tile's first barrier publishes them
-    const int nt = tiles_x * tiles_y, total = nt * C;
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int c = item / nt;
-        fused_item<P, NMB, NBLK, FP8>(img, H, W, bp, scale, a, lds_w16, lds_bias, fields2, out, tiles_x,
-                                      item - c * nt, c);
-    }
+    const int nt = tiles_x * tiles_y;
+    for (int item = blockIdx.x; item < nt; item += gridDim.x)
+        fused_item<P, NMB, NBLK, FP8>(img, C, H, W, bp, scale, a, lds_w16, lds_bias, fields2, out, tiles_x, item);
 }
 
 template <int P, int NMB, int NBLK, bool FP8>
@@ -609,11 +644,8 @@ __global__ void __launch_bounds__(256) blur_mlp_batch(const FrameDesc* __restric
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int f = find_frame(first, n, item);
         const FrameDesc& d = fr[f];
-        const int l = item - first[f];
-        const int nt = d.tiles_x * d.tiles_y;
-        const int c = l / nt;
-        fused_item<P, NMB, NBLK, FP8>(d.image, d.H, d.W, bp, scale, a, lds_w16, lds_bias,
-                                      d.fields + 2 * (size_t)d.H * d.W, d.blurred, d.tiles_x, l - c * nt, c);
+        fused_item<P, NMB, NBLK, FP8>(d.image, d.C, d.H, d.W, bp, scale, a, lds_w16, lds_bias,
+                                      d.fields + 2 * (size_t)d.H * d.W, d.blurred, d.tiles_x, item - first[f]);
     }
 }
 
@@ -763,17 +795,31 @@ namespace {
 // Pixel blocks per wave of the fused BF16 kernel: the blur accumulators
 // (4 NBLK NMB registers) and the network's live values must share the wave's
 // 256 accumulation-capable registers, so wide bases take 12-row or 8-row tiles.
-constexpr int fused_nblk_bf16(int nmb) { return nmb >= 8 ? 2 : (nmb >= 5 ? 4 : 8); }
-constexpr int fused_nblk_fp8(int nmb) { return nmb >= 7 ? 2 : 4; }
+constexpr int fused_nblk_bf16(int nmb) { return nmb >= 8 ? 2 : (nmb >= 4 ? 4 : 8); }
+constexpr int fused_nblk_fp8(int nmb) { return nmb >= 5 ? 2 : 4; }
+// FP8 instances whose registers fit without spilling (the others use the
+// network kernel and the w-reading blur)
+constexpr bool fused_fp8_fits(int P, int nmb) { return nmb <= 7 && !(P == 17 && nmb >= 4); }
 
 template <int P, int NMB>
 const void* fused_fn_nmb(p2s_precision prec, bool batch) {
-    if (prec == P2S_FP8E4M3) {
-        constexpr int NBLK = fused_nblk_fp8(NMB);
-        return batch ? (const void*)blur_mlp_batch<P, NMB, NBLK, true> : (const void*)blur_mlp_kernel<P, NMB, NBLK, true>;
+    // (the discarded branches are not instantiated)
+    if constexpr (16 * (NMB - 1) + 1 > P * P) {
+        return nullptr;                          // more basis functions than taps: not a basis
+    } else {
+        if (prec == P2S_FP8E4M3) {
+            if constexpr (!fused_fp8_fits(P, NMB)) {
+                return nullptr;
+            } else {
+                constexpr int NBLK = fused_nblk_fp8(NMB);
+                return batch ? (const void*)blur_mlp_batch<P, NMB, NBLK, true>
+                             : (const void*)blur_mlp_kernel<P, NMB, NBLK, true>;
+            }
+        }
+        constexpr int NBLK = fused_nblk_bf16(NMB);
+        return batch ? (const void*)blur_mlp_batch<P, NMB, NBLK, false>
+                     : (const void*)blur_mlp_kernel<P, NMB, NBLK, false>;
     }
-    constexpr int NBLK = fused_nblk_bf16(NMB);
-    return batch ? (const void*)blur_mlp_batch<P, NMB, NBLK, false> : (const void*)blur_mlp_kernel<P, NMB, NBLK, false>;
 }
 
 template <int P>
@@ -856,7 +902,7 @@ hipError_t launch_blur_mlp(const Basis& b, const Mlp& m, p2s_precision prec, con
     fill_weight_args(m, P2S_BF16, a);
     const int TY = blur_mlp_tile_rows(prec, b.nmb);
     int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + TY - 1) / TY;
-    const int items = tiles_x * tiles_y * C;
+    const int items = tiles_x * tiles_y;            // each covers all channels of its tile
     const int grid = std::min(items, resident_workgroups(fn, 256, network_lds_bytes(m)));
     const uint4* bp = reinterpret_cast<const uint4*>(prec == P2S_BF16 ? (const void*)b.bf16 : (const void*)b.fp8);
     const int* scale = b.fp8_scale;

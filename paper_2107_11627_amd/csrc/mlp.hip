@@ -160,46 +160,112 @@ __global__ void __launch_bounds__(kWaves * 64) mlp_f32_batch(MlpArgs a, const Fr
 }
 
 // ------------------------------------------------------------------ BF16
+// One wave per SIMD, 4 pixel blocks per wave (the same 256-pixel groups as
+// FP32): the evaluation interleaves its own VALU work with its MFMAs, so it
+// needs no second wave to hide latency, and the next group's inputs are
+// loaded before the current group is evaluated.
+constexpr int kWaves16 = 4;
+constexpr int kNb16 = kPixPerGroup / (kWaves16 * 16);
+
 template <int MB>
-__device__ __forceinline__ void mlp_bf16_group(const MlpArgs& a, const uint4* __restrict__ lds_w16,
-                                               const float* __restrict__ bias, const float* __restrict__ fields,
-                                               float* __restrict__ wout, int HW, int grp) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 4, m = lane & 15;
-    const int pix0 = grp * kPixPerGroup + wave * kNb * 16;
-    int pixc[kNb];
+__device__ __forceinline__ void store_w16(const float (&act)[kNb16][MB][4], float* __restrict__ wout, int pix0,
+                                          int m, int g, int HW, int K) {
 #pragma unroll
-    for (int nb = 0; nb < kNb; ++nb) pixc[nb] = min(pix0 + nb * 16 + m, HW - 1);
-    float outv[kNb][MB][4];
-    mlp_bf16_blocks<MB, kNb>(a, lds_w16, bias, fields, HW, pixc, outv);
-    store_w<MB>(outv, wout, pix0, m, g, HW, a.K);
+    for (int nb = 0; nb < kNb16; ++nb) {
+        const int pix = pix0 + nb * 16 + m;
+        if (pix >= HW) continue;
+        float* dst = wout + (size_t)pix * K;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int k = 16 * mb + 4 * g;
+            if ((K & 3) == 0) {
+                if (k < K)
+                    *reinterpret_cast<float4*>(dst + k) =
+                        make_float4(act[nb][mb][0], act[nb][mb][1], act[nb][mb][2], act[nb][mb][3]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (k + i < K) dst[k + i] = act[nb][mb][i];
+            }
+        }
+    }
+}
+
+// The wave's blocks two at a time: two blocks need about half the registers
+// of a SIMD (two activation sets), four would need all of them.
+template <int MB>
+__device__ __forceinline__ void eval_halves(const MlpArgs& a, const uint4* __restrict__ lds_w16,
+                                            const float* __restrict__ bias, const float (&in)[kNb16][2][8],
+                                            float (&out)[kNb16][MB][4]) {
+#pragma unroll
+    for (int b0 = 0; b0 < kNb16; b0 += 2) {
+        const float (&ig)[2][2][8] = *reinterpret_cast<const float (*)[2][2][8]>(&in[b0]);
+        float (&og)[2][MB][4] = *reinterpret_cast<float (*)[2][MB][4]>(&out[b0]);
+        mlp_bf16_eval<MB, 2>(a, lds_w16, bias, ig, og);
+    }
+}
+
+__device__ __forceinline__ void bf16_group_pixels(int grp, int HW, int (&pixc)[kNb16], int& pix0) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    pix0 = grp * kPixPerGroup + wave * kNb16 * 16;
+#pragma unroll
+    for (int nb = 0; nb < kNb16; ++nb) pixc[nb] = min(pix0 + nb * 16 + (lane & 15), HW - 1);
 }
 
 template <int MB>
-__global__ void __launch_bounds__(kWaves * 64) mlp_bf16_kernel(MlpArgs a, const float* __restrict__ fields,
-                                                               const uint4* __restrict__ wg,
-                                                               const float* __restrict__ bias,
-                                                               float* __restrict__ wout) {
+__global__ void __launch_bounds__(kWaves16 * 64) mlp_bf16_kernel(MlpArgs a, const float* __restrict__ fields,
+                                                                 const uint4* __restrict__ wg,
+                                                                 const float* __restrict__ bias,
+                                                                 float* __restrict__ wout) {
     extern __shared__ uint4 lds_w16[];
     const float* lds_bias = stage_bf16_network(lds_w16, a, wg, bias);
     __syncthreads();
-    for (int grp = blockIdx.x; grp < a.ngroups; grp += gridDim.x)
-        mlp_bf16_group<MB>(a, lds_w16, lds_bias, fields, wout, a.HW, grp);
+    const int lane = threadIdx.x & 63;
+    int pixc[kNb16], pix0;
+    float in[kNb16][2][8];
+    int grp = blockIdx.x;
+    if (grp < a.ngroups) {
+        bf16_group_pixels(grp, a.HW, pixc, pix0);
+        mlp_load_inputs<kNb16>(a, fields, a.HW, pixc, in);
+    }
+    for (; grp < a.ngroups; grp += gridDim.x) {
+        float cur[kNb16][2][8];
+#pragma unroll
+        for (int nb = 0; nb < kNb16; ++nb)
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) cur[nb][kc][e] = in[nb][kc][e];
+        const int cur0 = pix0;
+        if (grp + (int)gridDim.x < a.ngroups) {
+            bf16_group_pixels(grp + gridDim.x, a.HW, pixc, pix0);
+            mlp_load_inputs<kNb16>(a, fields, a.HW, pixc, in);
+        }
+        float outv[kNb16][MB][4];
+        eval_halves<MB>(a, lds_w16, lds_bias, cur, outv);
+        store_w16<MB>(outv, wout, cur0, lane & 15, lane >> 4, a.HW, a.K);
+    }
 }
 
 template <int MB>
-__global__ void __launch_bounds__(kWaves * 64) mlp_bf16_batch(MlpArgs a, const FrameDesc* __restrict__ fr,
-                                                              const int* __restrict__ first, int n,
-                                                              const uint4* __restrict__ wg,
-                                                              const float* __restrict__ bias) {
+__global__ void __launch_bounds__(kWaves16 * 64) mlp_bf16_batch(MlpArgs a, const FrameDesc* __restrict__ fr,
+                                                                const int* __restrict__ first, int n,
+                                                                const uint4* __restrict__ wg,
+                                                                const float* __restrict__ bias) {
     extern __shared__ uint4 lds_w16[];
     const float* lds_bias = stage_bf16_network(lds_w16, a, wg, bias);
     __syncthreads();
+    const int lane = threadIdx.x & 63;
     const int total = first[n];
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int f = find_frame(first, n, item);
         const int HW = fr[f].H * fr[f].W;
-        mlp_bf16_group<MB>(a, lds_w16, lds_bias, fr[f].fields + 2 * (size_t)HW, fr[f].w, HW, item - first[f]);
+        int pixc[kNb16], pix0;
+        bf16_group_pixels(item - first[f], HW, pixc, pix0);
+        float in[kNb16][2][8], outv[kNb16][MB][4];
+        mlp_load_inputs<kNb16>(a, fr[f].fields + 2 * (size_t)HW, HW, pixc, in);
+        eval_halves<MB>(a, lds_w16, lds_bias, in, outv);
+        store_w16<MB>(outv, fr[f].w, pix0, lane & 15, lane >> 4, HW, a.K);
     }
 }
 
@@ -248,7 +314,7 @@ hipError_t launch_mb_batch(const Mlp& mm, const MlpArgs& a0, const BatchLaunch& 
         hipLaunchKernelGGL(mlp_f32_batch<MB>, dim3(bl.grid[ST_MLP]), dim3(kWaves * 64), mm.bytes32, s, a, bl.frames,
                            first, bl.n, mm.w32, mm.bias);
     else
-        hipLaunchKernelGGL(mlp_bf16_batch<MB>, dim3(bl.grid[ST_MLP]), dim3(kWaves * 64),
+        hipLaunchKernelGGL(mlp_bf16_batch<MB>, dim3(bl.grid[ST_MLP]), dim3(kWaves16 * 64),
                            mm.bytes16 + 4 * (size_t)a.nbias, s, a, bl.frames,
                            first, bl.n, reinterpret_cast<const uint4*>(mm.w16), mm.bias);
     return hipGetLastError();
@@ -260,7 +326,7 @@ hipError_t launch_mb(const Mlp& mm, const MlpArgs& a0, const float* fields, p2s_
     hipError_t e0 = set_attrs<MB>();
     if (e0 != hipSuccess) return e0;
     MlpArgs a = a0;
-    const int grid = std::min(a.ngroups, num_cus() * 2);
+    const int grid = std::min(a.ngroups, mlp_batch_resident(mm, prec));
     if (prec == P2S_FP32) {
         for (int l = 0; l < mm.L; ++l) a.woff[l] = (int)(mm.off32[l] / sizeof(float));
         a.nkc0 = mm.nkc32[0];
@@ -269,7 +335,7 @@ hipError_t launch_mb(const Mlp& mm, const MlpArgs& a0, const float* fields, p2s_
                            mm.bias, w);
     } else {
         fill_weight_args(mm, prec, a);
-        hipLaunchKernelGGL(mlp_bf16_kernel<MB>, dim3(grid), dim3(kWaves * 64), mm.bytes16 + 4 * (size_t)a.nbias, s,
+        hipLaunchKernelGGL(mlp_bf16_kernel<MB>, dim3(grid), dim3(kWaves16 * 64), mm.bytes16 + 4 * (size_t)a.nbias, s,
                            a, fields, reinterpret_cast<const uint4*>(mm.w16), mm.bias, w);
     }
     return hipGetLastError();
@@ -292,8 +358,9 @@ int mlp_pixels_per_group() { return kPixPerGroup; }
 
 int mlp_batch_resident(const Mlp& mm, p2s_precision prec) {
     (void)mm;
-    (void)prec;
-    return 2 * num_cus();   // weights staged once per workgroup; LDS allows at most two
+    // weights staged once per workgroup; FP32: LDS allows two per CU, BF16:
+    // one (its waves need the whole register file of their SIMD)
+    return prec == P2S_FP32 ? 2 * num_cus() : num_cus();
 }
 
 hipError_t launch_mlp_batch(const Mlp& mm, const BatchLaunch& bl, p2s_precision prec, hipStream_t s) {
