@@ -122,7 +122,7 @@ int band_half(int N, double corr_len) {
 
 int band_size(int N, double corr_len) { return std::min(N, 2 * band_half(N, corr_len) + 1); }
 
-// Intermediate of the field generator: complex [pairs][H][band columns],
+// Intermediate of the field generator: complex [pairs][band columns][H],
 // followed by the Nfx twiddle factors of the row transforms.
 size_t fields_ws(int H, int W, int nz, const Params& pr) {
     const int Nfx = grid_of(W, pr.corr_len);

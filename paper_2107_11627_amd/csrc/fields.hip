@@ -76,100 +76,181 @@ __device__ __forceinline__ float2 bin_noise(int kx, int ky, int q, uint32_t k0, 
     return make_float2(r * c, r * s);
 }
 
+// Band index of an FFT bin (bins 0..kc and N-(M-1-kc)..N-1 hold band
+// entries 0..M-1), or -1 outside the band.
+__device__ __forceinline__ int bin_to_band(int b, int kc, int N, int M) {
+    if (b <= kc) return b < M ? b : -1;
+    const int j = b - (N - M);
+    return j > kc && j < M ? j : -1;
+}
 __device__ __forceinline__ int band_to_bin(int j, int kc, int N, int M) { return j <= kc ? j : j + (N - M); }
 
-// One Stockham pass of radix R over 2^lg_nfft transforms of length N stored
-// at stride ld; each transform gets blockDim >> lg_nfft threads.  Ns = product
-// of the radices already applied; tw[q] = exp(-2 pi i q / N); sgn = -1
-// forward, +1 inverse.  j / Ns is formed as floor((j + 0.5) / Ns) in FP32,
-// exact for the sizes here (the fraction stays >= 0.5/Ns from an integer).
+// Inverse (sgn = +1) or forward (sgn = -1) DFTs of 2, 3, 4, 5, 8 and 9
+// points in registers: X[k] = sum_n x[n] exp(sgn 2 pi i n k / R).
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+__device__ __forceinline__ void dft3(float2& a, float2& b, float2& c, float sgn) {
+    const float s3 = 0.86602540378443864676f;
+    const float2 t1 = cadd(b, c);
+    const float2 t2 = make_float2(a.x - 0.5f * t1.x, a.y - 0.5f * t1.y);
+    const float2 t3 = mul_i(make_float2(s3 * (b.x - c.x), s3 * (b.y - c.y)), sgn);
+    a = cadd(a, t1);
+    b = cadd(t2, t3);
+    c = csub(t2, t3);
+}
+
+__device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d, float sgn) {
+    const float2 s0 = cadd(a, c), d0 = csub(a, c), s1 = cadd(b, d);
+    const float2 d1 = mul_i(csub(b, d), sgn);
+    a = cadd(s0, s1);
+    c = csub(s0, s1);
+    b = cadd(d0, d1);
+    d = csub(d0, d1);
+}
+
 template <int R>
-__device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, float2* __restrict__ dst, int N,
-                                              int ld, int lg_nfft, int Ns, const float2* __restrict__ tw,
-                                              float sgn) {
-    const int nb = N / R;
-    const int step = N / (Ns * R);
-    const float inv_ns = 1.0f / (float)Ns;
-    const int lg_tpf = __builtin_ctz(blockDim.x) - lg_nfft;
-    const int f = threadIdx.x >> lg_tpf;
-    const int tpf = 1 << lg_tpf;
-    const float2* s = src + f * ld;
-    float2* d = dst + f * ld;
-    for (int j = threadIdx.x & (tpf - 1); j < nb; j += tpf) {
-        const int qj = __float2int_rd(((float)j + 0.5f) * inv_ns);
-        const int k = j - qj * Ns;
-        float2 v[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            float2 x = s[j + r * nb];
-            if (r > 0) {
-                float2 w = tw[r * k * step];
-                w.y *= -sgn;   // table holds exp(-i..); inverse uses the conjugate
-                x = cmul(x, w);
-            }
-            v[r] = x;
-        }
-        float2 o[R];
-        if constexpr (R == 2) {
-            o[0] = make_float2(v[0].x + v[1].x, v[0].y + v[1].y);
-            o[1] = make_float2(v[0].x - v[1].x, v[0].y - v[1].y);
-        } else if constexpr (R == 4) {
-            const float2 a = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
-            const float2 b = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
-            const float2 c = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
-            const float2 dd = mul_i(make_float2(v[1].x - v[3].x, v[1].y - v[3].y), sgn);
-            o[0] = make_float2(a.x + c.x, a.y + c.y);
-            o[2] = make_float2(a.x - c.x, a.y - c.y);
-            o[1] = make_float2(b.x + dd.x, b.y + dd.y);
-            o[3] = make_float2(b.x - dd.x, b.y - dd.y);
-        } else if constexpr (R == 3) {
-            const float s3 = 0.86602540378443864676f;
-            const float2 t1 = make_float2(v[1].x + v[2].x, v[1].y + v[2].y);
-            const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
-            const float2 t3 = mul_i(make_float2(s3 * (v[1].x - v[2].x), s3 * (v[1].y - v[2].y)), sgn);
-            o[0] = make_float2(v[0].x + t1.x, v[0].y + t1.y);
-            o[1] = make_float2(t2.x + t3.x, t2.y + t3.y);
-            o[2] = make_float2(t2.x - t3.x, t2.y - t3.y);
-        } else {   // R == 5
-            const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
-            const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
-            const float2 a1 = make_float2(v[1].x + v[4].x, v[1].y + v[4].y);
-            const float2 b1 = make_float2(v[1].x - v[4].x, v[1].y - v[4].y);
-            const float2 a2 = make_float2(v[2].x + v[3].x, v[2].y + v[3].y);
-            const float2 b2 = make_float2(v[2].x - v[3].x, v[2].y - v[3].y);
-            o[0] = make_float2(v[0].x + a1.x + a2.x, v[0].y + a1.y + a2.y);
-            const float2 p1 = make_float2(v[0].x + c1 * a1.x + c2 * a2.x, v[0].y + c1 * a1.y + c2 * a2.y);
-            const float2 p2 = make_float2(v[0].x + c2 * a1.x + c1 * a2.x, v[0].y + c2 * a1.y + c1 * a2.y);
-            const float2 q1 = mul_i(make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y), sgn);
-            const float2 q2 = mul_i(make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y), sgn);
-            o[1] = make_float2(p1.x + q1.x, p1.y + q1.y);
-            o[4] = make_float2(p1.x - q1.x, p1.y - q1.y);
-            o[2] = make_float2(p2.x + q2.x, p2.y + q2.y);
-            o[3] = make_float2(p2.x - q2.x, p2.y - q2.y);
-        }
-        const int base = qj * Ns * R + k;
-#pragma unroll
-        for (int q = 0; q < R; ++q) d[base + q * Ns] = o[q];
+__device__ __forceinline__ void dft(float2 (&v)[R], float sgn) {
+    if constexpr (R == 2) {
+        const float2 t = v[0];
+        v[0] = cadd(t, v[1]);
+        v[1] = csub(t, v[1]);
+    } else if constexpr (R == 3) {
+        dft3(v[0], v[1], v[2], sgn);
+    } else if constexpr (R == 4) {
+        dft4(v[0], v[1], v[2], v[3], sgn);
+    } else if constexpr (R == 5) {
+        const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+        const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
+        const float2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+        const float2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+        const float2 x0 = v[0];
+        v[0] = cadd(x0, cadd(a1, a2));
+        const float2 p1 = make_float2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+        const float2 p2 = make_float2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+        const float2 q1 = mul_i(make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y), sgn);
+        const float2 q2 = mul_i(make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y), sgn);
+        v[1] = cadd(p1, q1);
+        v[4] = csub(p1, q1);
+        v[2] = cadd(p2, q2);
+        v[3] = csub(p2, q2);
+    } else if constexpr (R == 8) {
+        // even and odd halves, then W8^k on the odd one
+        float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+        float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+        dft4(e0, e1, e2, e3, sgn);
+        dft4(o0, o1, o2, o3, sgn);
+        const float h = 0.70710678118654752440f;
+        o1 = make_float2(h * (o1.x - sgn * o1.y), h * (o1.y + sgn * o1.x));     // * (1 + sgn i) / sqrt 2
+        o2 = mul_i(o2, sgn);                                                      // * sgn i
+        o3 = make_float2(-h * (o3.x + sgn * o3.y), h * (sgn * o3.x - o3.y));    // * (-1 + sgn i) / sqrt 2
+        v[0] = cadd(e0, o0);
+        v[4] = csub(e0, o0);
+        v[1] = cadd(e1, o1);
+        v[5] = csub(e1, o1);
+        v[2] = cadd(e2, o2);
+        v[6] = csub(e2, o2);
+        v[3] = cadd(e3, o3);
+        v[7] = csub(e3, o3);
+    } else {                                     // R == 9: 3 x 3
+        // X[k2 + 3 k1] = sum_n1 W3^(n1 k1) W9^(n1 k2) sum_n2 x[n1 + 3 n2] W3^(n2 k2)
+        dft3(v[0], v[3], v[6], sgn);
+        dft3(v[1], v[4], v[7], sgn);
+        dft3(v[2], v[5], v[8], sgn);
+        const float c1 = 0.76604444311897803520f, s1 = 0.64278760968653932632f;   // cos, sin 2 pi / 9
+        const float c2 = 0.17364817766693034885f, s2 = 0.98480775301220805936f;   // 4 pi / 9
+        const float c4 = -0.93969262078590838405f, s4 = 0.34202014332566873304f;  // 8 pi / 9
+        auto rot = [&](float2 x, float c, float sn) {
+            return make_float2(c * x.x - sgn * sn * x.y, c * x.y + sgn * sn * x.x);
+        };
+        v[4] = rot(v[4], c1, s1);                // n1 = 1, k2 = 1
+        v[7] = rot(v[7], c2, s2);                // n1 = 1, k2 = 2
+        v[5] = rot(v[5], c2, s2);                // n1 = 2, k2 = 1
+        v[8] = rot(v[8], c4, s4);                // n1 = 2, k2 = 2
+        dft3(v[0], v[1], v[2], sgn);             // k2 = 0 -> X0, X3, X6
+        dft3(v[3], v[4], v[5], sgn);             // k2 = 1 -> X1, X4, X7
+        dft3(v[6], v[7], v[8], sgn);             // k2 = 2 -> X2, X5, X8
+        const float2 x0 = v[0], x3 = v[1], x6 = v[2], x1 = v[3], x4 = v[4], x7 = v[5], x2 = v[6], x5 = v[7],
+                     x8 = v[8];
+        v[0] = x0; v[1] = x1; v[2] = x2; v[3] = x3; v[4] = x4; v[5] = x5; v[6] = x6; v[7] = x7; v[8] = x8;
     }
 }
 
-// Full transform of 2^lg_nfft sequences; returns the buffer with the result.
-__device__ float2* fft_batch(float2* a, float2* b, int N, int ld, int lg_nfft, const int* rad, int nrad,
-                             const float2* tw, float sgn) {
-    int Ns = 1;
-    for (int i = 0; i < nrad; ++i) {
-        const int R = rad[i];
-        if (R == 4) stockham_pass<4>(a, b, N, ld, lg_nfft, Ns, tw, sgn);
-        else if (R == 2) stockham_pass<2>(a, b, N, ld, lg_nfft, Ns, tw, sgn);
-        else if (R == 3) stockham_pass<3>(a, b, N, ld, lg_nfft, Ns, tw, sgn);
-        else stockham_pass<5>(a, b, N, ld, lg_nfft, Ns, tw, sgn);
+// One Stockham pass of radix R over the transforms of one work item, each of
+// length N with tpf = 2^lg_tpf threads; Ns = product of the radices already
+// applied.  Butterfly j reads x[j + r N/R] (src(f, index)), multiplies by
+// the twiddles W_N^(r k N/(Ns R)) (k = j mod Ns; none in the first pass, where
+// Ns = 1) and writes X[(j / Ns) Ns R + k + q Ns] (dst(f, index, value)).
+// j / Ns is formed as floor((j + 0.5) / Ns) in FP32, exact for these sizes.
+// tw[q] = exp(-2 pi i q / N); the inverse (sgn = +1) conjugates it.
+template <int R, bool FIRST, class Src, class Dst>
+__device__ __forceinline__ void stockham(int N, int Ns, int lg_tpf, const float2* __restrict__ tw, float sgn,
+                                         Src&& src, Dst&& dst) {
+    const int nb = N / R;
+    const int f = threadIdx.x >> lg_tpf;
+    const int tpf = 1 << lg_tpf;
+    const int step = nb / Ns;
+    const float inv_ns = 1.0f / (float)Ns;
+    for (int j = threadIdx.x & (tpf - 1); j < nb; j += tpf) {
+        float2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = src(f, j + r * nb);
+        int base = j * R;
+        if constexpr (!FIRST) {
+            const int qj = __float2int_rd(((float)j + 0.5f) * inv_ns);
+            const int k = j - qj * Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[r * k * step];
+                w.y *= -sgn;
+                v[r] = cmul(v[r], w);
+            }
+            base = qj * Ns * R + k;
+        }
+        dft<R>(v, sgn);
+#pragma unroll
+        for (int q = 0; q < R; ++q) dst(f, base + q * Ns, v[q]);
+    }
+}
+
+template <bool FIRST, class Src, class Dst>
+__device__ __forceinline__ void stockham_r(int R, int N, int Ns, int lg_tpf, const float2* tw, float sgn, Src&& src,
+                                           Dst&& dst) {
+    switch (R) {
+        case 2: stockham<2, FIRST>(N, Ns, lg_tpf, tw, sgn, src, dst); break;
+        case 3: stockham<3, FIRST>(N, Ns, lg_tpf, tw, sgn, src, dst); break;
+        case 4: stockham<4, FIRST>(N, Ns, lg_tpf, tw, sgn, src, dst); break;
+        case 5: stockham<5, FIRST>(N, Ns, lg_tpf, tw, sgn, src, dst); break;
+        case 8: stockham<8, FIRST>(N, Ns, lg_tpf, tw, sgn, src, dst); break;
+        default: stockham<9, FIRST>(N, Ns, lg_tpf, tw, sgn, src, dst); break;
+    }
+}
+
+// Whole inverse transforms of one item: the first pass gathers its inputs
+// with src (band entries or zero), the middle passes run LDS to LDS at
+// stride ld, the last pass hands every output to out(f, index, value).
+// At least two passes (N >= 72 > the largest radix).
+template <class Src, class Out>
+__device__ __forceinline__ void ifft_item(int N, int ld, int lg_tpf, const int* rad, int nrad, const float2* tw,
+                                          float2* a, float2* b, Src&& src, Out&& out) {
+    auto to_lds = [&](float2* buf) {
+        return [buf, ld](int f, int i, float2 v) { buf[f * ld + i] = v; };
+    };
+    auto from_lds = [&](const float2* buf) {
+        return [buf, ld](int f, int i) { return buf[f * ld + i]; };
+    };
+    stockham_r<true>(rad[0], N, 1, lg_tpf, tw, 1.0f, src, to_lds(a));
+    __syncthreads();
+    int Ns = rad[0];
+    for (int i = 1; i + 1 < nrad; ++i) {
+        stockham_r<false>(rad[i], N, Ns, lg_tpf, tw, 1.0f, from_lds(a), to_lds(b));
         __syncthreads();
         float2* t = a;
         a = b;
         b = t;
-        Ns *= R;
+        Ns *= rad[i];
     }
-    return a;
+    stockham_r<false>(rad[nrad - 1], N, Ns, lg_tpf, tw, 1.0f, from_lds(a), out);
 }
 
 __device__ void fill_twiddles(float2* tw, int N) {
@@ -190,9 +271,12 @@ __device__ __forceinline__ float gauss_filter(int k, int N, float corr_len) {
 
 __device__ __forceinline__ int ld_of(int N) { return N | 1; }   // odd stride spreads LDS banks
 
-// Column work item: plane pair q, band columns j0 .. j0 + 2^lg_cpb - 1.  Noise
-// spectrum of those columns -> inverse FFT along y -> V.  Item (q=0, j0=0)
-// also publishes the row transforms' twiddle table.
+// Column work item: plane pair q, band columns j0 .. j0 + 2^lg_cpb - 1.  The
+// first pass draws the noise of the band rows times the separable filter
+// (zero elsewhere), the transform runs along y, the last pass writes
+// V[q][j][y] for y < H (column-major, so consecutive threads write
+// consecutive y).  Item (q=0, j0=0) also publishes the row transforms'
+// twiddle table.
 __device__ __forceinline__ void fields_cols_item(const FieldPlan& fp, float2* __restrict__ V, float2* __restrict__ twx_out,
                                  int lg_cpb, int q, int j0, float2* smem, bool fresh) {
     const int cpb = 1 << lg_cpb;
@@ -213,35 +297,29 @@ __device__ __forceinline__ void fields_cols_item(const FieldPlan& fp, float2* __
         for (int k = threadIdx.x; k < N; k += blockDim.x) filt[k] = gauss_filter(k, N, fp.corr_len);
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < cpb * N; idx += blockDim.x) {
-        const int c = idx / N;                 // small: cpb <= 8
-        const int ky = idx - c * N;
+    const int lg_tpf = 8 - lg_cpb;             // 256 threads
+    auto noise = [&](int c, int ky) -> float2 {
         const int j = j0 + c;
         const int kyw = ky < (N + 1) / 2 ? ky : N - ky;
-        float2 v = make_float2(0.f, 0.f);
-        if (j < fp.Mx && kyw <= fp.kcy) {
-            const int kx = band_to_bin(j, fp.kcx, fp.Nfx, fp.Mx);
-            const float h = gauss_filter(kx, fp.Nfx, fp.corr_len) * filt[ky] * fp.norm;
-            const float2 z = bin_noise(kx, ky, q, fp.k0, fp.k1);
-            v = make_float2(h * z.x, h * z.y);
-        }
-        buf0[c * ld + ky] = v;
-    }
-    __syncthreads();
-    const float2* X = fft_batch(buf0, buf1, N, ld, lg_cpb, fp.rad_y, fp.nrad_y, tw, 1.0f);
+        if (j >= fp.Mx || kyw > fp.kcy) return make_float2(0.f, 0.f);
+        const int kx = band_to_bin(j, fp.kcx, fp.Nfx, fp.Mx);
+        const float h = gauss_filter(kx, fp.Nfx, fp.corr_len) * filt[ky] * fp.norm;
+        const float2 z = bin_noise(kx, ky, q, fp.k0, fp.k1);
+        return make_float2(h * z.x, h * z.y);
+    };
     const int H = fp.H, Mx = fp.Mx;
-    float2* Vq = V + (size_t)q * H * Mx;
-    for (int idx = threadIdx.x; idx < H * cpb; idx += blockDim.x) {
-        const int y = idx >> lg_cpb;
-        const int c = idx & (cpb - 1);
+    float2* Vq = V + (size_t)q * Mx * H;
+    auto out = [&](int c, int y, float2 v) {
         const int j = j0 + c;
-        if (j < Mx) Vq[(size_t)y * Mx + j] = X[c * ld + y];
-    }
+        if (y < H && j < Mx) Vq[(size_t)j * H + y] = v;
+    };
+    ifft_item(N, ld, lg_tpf, fp.rad_y, fp.nrad_y, tw, buf0, buf1, noise, out);
     __syncthreads();                           // LDS free for the next item
 }
 
-// Row work item: plane pair q, output rows y0 .. y0 + 2^lg_rpb - 1.  V scattered
-// into the band bins -> inverse FFT along x -> planes 2q, 2q+1.
+// Row work item: plane pair q, output rows y0 .. y0 + 2^lg_rpb - 1.  The first
+// pass gathers the band entries of V (zero elsewhere), the transform runs
+// along x, the last pass writes planes 2q, 2q+1 for x < W.
 __device__ __forceinline__ void fields_rows_item(const FieldPlan& fp, const float2* __restrict__ V, float* __restrict__ F,
                                  const float2* __restrict__ twx, int lg_rpb, int q, int y0, float2* smem, bool fresh) {
     const int rpb = 1 << lg_rpb;
@@ -249,35 +327,30 @@ __device__ __forceinline__ void fields_rows_item(const FieldPlan& fp, const floa
     float2* buf0 = smem;
     float2* buf1 = smem + rpb * ld;
     float2* tw = smem + 2 * rpb * ld;
-    const int H = fp.H, W = fp.W, Mx = fp.Mx;
-    if (fresh)                                 // first item of this frame in the workgroup
+    const int H = fp.H, W = fp.W, Mx = fp.Mx, kcx = fp.kcx;
+    if (fresh) {                               // first item of this frame in the workgroup
         for (int k = threadIdx.x; k < N; k += blockDim.x) tw[k] = twx[k];
-    for (int idx = threadIdx.x; idx < rpb * ld; idx += blockDim.x) buf0[idx] = make_float2(0.f, 0.f);
-    __syncthreads();
-    const float2* Vq = V + (size_t)q * H * Mx;
-    for (int idx = threadIdx.x; idx < rpb * Mx; idx += blockDim.x) {
-        const int r = idx / Mx;                // small: rpb <= 8
-        const int j = idx - r * Mx;
-        const int y = y0 + r;
-        if (y < H) buf0[r * ld + band_to_bin(j, fp.kcx, N, Mx)] = Vq[(size_t)y * Mx + j];
+        __syncthreads();
     }
-    __syncthreads();
-    const float2* X = fft_batch(buf0, buf1, N, ld, lg_rpb, fp.rad_x, fp.nrad_x, tw, 1.0f);
+    const float2* Vq = V + (size_t)q * Mx * H;
+    auto band = [&](int r, int b) -> float2 {
+        const int y = y0 + r;
+        const int j = bin_to_band(b, kcx, N, Mx);
+        return (y < H && j >= 0) ? Vq[(size_t)j * H + y] : make_float2(0.f, 0.f);
+    };
     const int p0 = 2 * q, p1 = 2 * q + 1;
     const float s0 = fp.sigma[p0];
     const bool has1 = p1 < fp.nplanes;
     const float s1 = has1 ? fp.sigma[p1] : 0.0f;
     float* F0 = F + (size_t)p0 * H * W;
     float* F1 = F + (size_t)p1 * H * W;
-    for (int r = 0; r < rpb; ++r) {
+    auto out = [&](int r, int x, float2 v) {
         const int y = y0 + r;
-        if (y >= H) break;
-        for (int x = threadIdx.x; x < W; x += blockDim.x) {
-            const float2 v = X[r * ld + x];
-            F0[(size_t)y * W + x] = s0 * v.x;
-            if (has1) F1[(size_t)y * W + x] = s1 * v.y;
-        }
-    }
+        if (y >= H || x >= W) return;
+        F0[(size_t)y * W + x] = s0 * v.x;
+        if (has1) F1[(size_t)y * W + x] = s1 * v.y;
+    };
+    ifft_item(N, ld, 8 - lg_rpb, fp.rad_x, fp.nrad_x, tw, buf0, buf1, band, out);
     __syncthreads();                           // LDS free for the next item
 }
 
@@ -389,8 +462,12 @@ hipError_t launch_fields_batch(const BatchLaunch& bl, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Radix passes for a 5-smooth length: 9s and 8s first (fewest passes), then
+// 4, 2, 3, 5 for what is left.
 int factor_radices(int n, int* rad) {
     int k = 0;
+    while (n % 9 == 0) { rad[k++] = 9; n /= 9; }
+    while (n % 8 == 0) { rad[k++] = 8; n /= 8; }
     while (n % 4 == 0) { rad[k++] = 4; n /= 4; }
     while (n % 2 == 0) { rad[k++] = 2; n /= 2; }
     while (n % 3 == 0) { rad[k++] = 3; n /= 3; }

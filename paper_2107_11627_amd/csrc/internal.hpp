@@ -92,7 +92,7 @@ struct FrameDesc {
     float* fields;                   // [nz][H][W]
     float* w;                        // [H*W][K]
     float* blurred;                  // [C][H][W]
-    float2* V;                       // field intermediate [pairs][H][Mx]
+    float2* V;                       // field intermediate [pairs][Mx][H]
     float2* twx;                     // [Nfx] row twiddles
     int C, H, W;
     int tiles_x, tiles_y;            // blur tiles
