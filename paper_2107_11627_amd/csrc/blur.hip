@@ -205,6 +205,54 @@ __device__ __forceinline__ void stage_window(float* __restrict__ dst, int ld, co
     }
 }
 
+// Rows of the staged fp32 window of a low-precision tile (P taps, 2 NBLK
+// output rows); the stage has a pitch of 64 floats (kTX + 2 R <= 64), one
+// row per wave-wide copy instruction.
+constexpr int kStagePitch = 64;
+template <int P, int NBLK>
+struct TileGeom {
+    static constexpr int R = (P - 1) / 2;
+    static constexpr int TY = NBLK * 2;
+    static constexpr int PH = TY + 2 * R;                 // rows of the row-chunk layout
+    static constexpr int QH = TY + 8 * ((P + 7) / 8 - 1); // rows of the column-chunk layout
+    static constexpr int SH = QH + 7 > PH ? QH + 7 : PH;  // staged rows
+    static_assert(kTX + 2 * R <= kStagePitch, "stage pitch");
+};
+
+template <int P, int NBLK>
+__device__ __forceinline__ float* stage_lds() {
+    return lds_buffer<float, TileGeom<P, NBLK>::SH * kStagePitch, 2>();
+}
+
+// The image window a tile item stages: rows y_lo.., columns x_lo.. of
+// channel plane ic (clamped to the image); ic == nullptr: no item.
+struct Window {
+    const float* ic;
+    int H, W, y_lo, x_lo;
+};
+
+// Start the copy of a window into the stage without registers: one
+// global_load_lds per row and wave (lane l copies column x_lo + l, clamped),
+// completed by s_waitcnt vmcnt(0) and a barrier before the stage is read.
+template <int SH>
+__device__ __forceinline__ void window_dma(float* stage, const Window& w) {
+    if (!w.ic) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nw = (int)(blockDim.x >> 6);
+    const int xx = min(max(w.x_lo + lane, 0), w.W - 1);
+    for (int r = wave; r < SH; r += nw) {
+        const int yy = min(max(w.y_lo + r, 0), w.H - 1);
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(w.ic + (size_t)yy * w.W + xx),
+                                         (__attribute__((address_space(3))) void*)(stage + r * kStagePitch), 4, 0, 0);
+    }
+}
+
+__device__ __forceinline__ void wait_window() {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+}
+
 // ------------------------------------------------------------------ FP32
 // LDS tile of the image with a halo of R on every side (replicate border),
 // pitch padded by one float.  Tap u = 4 t + L/16 in row-major (dy, dx) order.
@@ -283,9 +331,10 @@ __device__ __forceinline__ void blur_f32_tile(const float* __restrict__ img, int
 // and column chunk q at ColPk[ly + 8 q][lx].  RowPk rows hold kTX + 8 (A8 - 1)
 // entries, ColPk rows kTX; a lane's per-pixel-block row step is the pitch of
 // the kind its chunk of the current step comes from.
-template <int P, int NMB, int NBLK, class Epi>
+template <int P, int NMB, int NBLK, bool DMA = false, class Epi>
 __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, int H, int W,
-                                               const uint4* __restrict__ bp, int tiles_x, int tile, int c, Epi&& epi) {
+                                               const uint4* __restrict__ bp, int tiles_x, int tile, int c, Epi&& epi,
+                                               const Window& next = Window{}) {
     constexpr int R = (P - 1) / 2;
     constexpr int A8 = P / 8;                    // row chunks per PSF row
     constexpr int NROW = P * A8;
@@ -296,12 +345,12 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
     constexpr int CPITCH = kTX;                  // column-chunk positions per row
     constexpr int PH = TY + 2 * R;               // rows of RowPk
     constexpr int QH = TY + 8 * (NCOL - 1);      // rows of ColPk
-    constexpr int SW = kTX + 2 * R;              // fp32 staging tile
-    constexpr int SH = (QH + 7 > PH ? QH + 7 : PH);
+    constexpr int SW = kStagePitch;              // fp32 staging tile pitch
+    constexpr int SH = TileGeom<P, NBLK>::SH;
     static_assert(P == 8 * A8 + 1, "bf16 layout needs P = 8a + 1");
     uint4* const rowpk = lds_buffer<uint4, PH * PITCH, 0>();
     uint4* const colpk = lds_buffer<uint4, QH * CPITCH, 1>();
-    float* const stage = lds_buffer<float, SH * SW, 2>();
+    float* const stage = stage_lds<P, NBLK>();
 
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x0 = tx * kTX, y0 = ty * TY;
@@ -312,11 +361,18 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
     const size_t HW = (size_t)H * W;
 
     {
-        const float* ic = img + c * HW;
-        epi.prefetch(y0 + lyw, x0, m);
-        __syncthreads();                          // previous item of a persistent workgroup done with LDS
-        stage_window<14>(stage, SW, ic, H, W, y0 - R, x0 - R, SH, SW);
-        __syncthreads();
+        if constexpr (DMA) {
+            // the window was started earlier (kernel prologue or previous
+            // item); the barrier also retires the previous item's LDS reads
+            wait_window();
+            epi.prefetch(y0 + lyw, x0, m);
+        } else {
+            const float* ic = img + c * HW;
+            epi.prefetch(y0 + lyw, x0, m);
+            __syncthreads();                      // previous item of a persistent workgroup done with LDS
+            stage_window<14>(stage, SW, ic, H, W, y0 - R, x0 - R, SH, kTX + 2 * R);
+            __syncthreads();
+        }
         for (int idx = threadIdx.x; idx < PH * PITCH; idx += blockDim.x) {
             const int r = idx / PITCH, p = idx - r * PITCH;
             const float* s = stage + r * SW + p;
@@ -330,6 +386,7 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
             colpk[r * CPITCH + q] = __builtin_bit_cast(uint4, to_bf16x8(v));
         }
         __syncthreads();
+        if constexpr (DMA) window_dma<SH>(stage, next);   // stage free until the next item
         floatx4 acc[NBLK][NMB];
         // B-operand source of chunk 4 t + g for this lane's pixel block 0, and
         // the row step of that kind of chunk
@@ -405,10 +462,10 @@ __device__ __forceinline__ uint2 pack_e4m3x8(const float* s, int stride) {
     return make_uint2(lo, hi);
 }
 
-template <int P, int NMB, int NBLK, class Epi>
+template <int P, int NMB, int NBLK, bool DMA = false, class Epi>
 __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int H, int W,
                                               const uint4* __restrict__ bp, const int* __restrict__ scale,
-                                              int tiles_x, int tile, int c, Epi&& epi) {
+                                              int tiles_x, int tile, int c, Epi&& epi, const Window& next = Window{}) {
     constexpr int R = (P - 1) / 2;
     constexpr int A8 = P / 8;
     constexpr int NROW = P * A8;
@@ -419,12 +476,12 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
     constexpr int PH = TY + 2 * R;
     constexpr int QH = TY + 8 * (NCOL - 1);
     constexpr int NR = PH > QH ? PH : QH;
-    constexpr int SW = kTX + 2 * R;
-    constexpr int SH = (QH + 7 > PH ? QH + 7 : PH);
+    constexpr int SW = kStagePitch;
+    constexpr int SH = TileGeom<P, NBLK>::SH;
     static_assert(P == 8 * A8 + 1, "fp8 layout needs P = 8a + 1");
     uint2* const rowpk8 = lds_buffer<uint2, NR * PITCH, 3>();
     uint2* const colpk8 = lds_buffer<uint2, NR * PITCH, 4>();
-    float* const stage8 = lds_buffer<float, SH * SW, 5>();
+    float* const stage8 = stage_lds<P, NBLK>();
 
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int x0 = tx * kTX, y0 = ty * TY;
@@ -434,11 +491,16 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
     const int lyw = wave * RPW;
     const size_t HW = (size_t)H * W;
 
-    const float* ic = img + c * HW;
-    epi.prefetch(y0 + lyw, x0, m);
-    __syncthreads();                              // previous item of a persistent workgroup done with LDS
-    stage_window<14>(stage8, SW, ic, H, W, y0 - R, x0 - R, SH, SW);
-    __syncthreads();
+    if constexpr (DMA) {
+        wait_window();                            // started earlier; also retires the previous item's LDS reads
+        epi.prefetch(y0 + lyw, x0, m);
+    } else {
+        const float* ic = img + c * HW;
+        epi.prefetch(y0 + lyw, x0, m);
+        __syncthreads();                          // previous item of a persistent workgroup done with LDS
+        stage_window<14>(stage8, SW, ic, H, W, y0 - R, x0 - R, SH, kTX + 2 * R);
+        __syncthreads();
+    }
     for (int idx = threadIdx.x; idx < PH * PITCH; idx += blockDim.x) {
         const int r = idx / PITCH, p = idx - r * PITCH;
         rowpk8[idx] = pack_e4m3x8(stage8 + r * SW + p, 1);
@@ -448,6 +510,7 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
         colpk8[r * PITCH + q] = pack_e4m3x8(stage8 + r * SW + q + 2 * R, SW);
     }
     __syncthreads();
+    if constexpr (DMA) window_dma<SH>(stage8, next);   // stage free until the next item
     int sc[NMB];
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb) sc[mb] = scale[16 * mb + m];
@@ -590,19 +653,32 @@ __global__ void __launch_bounds__(256) blur_fp8_batch(const FrameDesc* __restric
 // workgroups stage the packed network weights into dynamic LDS once, then
 // stride over the tiles of one frame, or over the (frame, tile) list of a
 // batch.  An item blurs every channel of its tile with the weights the
-// network produced once for the tile's pixels.
+// network produced once for the tile's pixels.  The image window of the next
+// (channel or item) is copied into the stage while the current one computes.
+template <int P, int NBLK>
+__device__ __forceinline__ Window tile_window(const float* plane, int H, int W, int tiles_x, int tile) {
+    constexpr int R = TileGeom<P, NBLK>::R, TY = TileGeom<P, NBLK>::TY;
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    return Window{plane, H, W, ty * TY - R, tx * kTX - R};
+}
+
 template <int P, int NMB, int NBLK, bool FP8>
 __device__ __forceinline__ void fused_item(const float* img, int C, int H, int W, const uint4* bp, const int* scale,
                                            const MlpArgs& a, const uint4* lds_w16, const float* bias,
-                                           const float* fields2, float* out, int tiles_x, int tile) {
+                                           const float* fields2, float* out, int tiles_x, int tile,
+                                           const Window& after) {
+    const size_t HW = (size_t)H * W;
+    auto next_of = [&](int c) {
+        return c + 1 < C ? tile_window<P, NBLK>(img + (c + 1) * HW, H, W, tiles_x, tile) : after;
+    };
     // channel 0 runs the network; the other channels reuse its weights (a
     // separate instance of the tile code, so that the network's registers
     // are not held across the channel loop)
     WFromNetwork<NMB, NBLK, true> first{&a, lds_w16, bias, fields2, H, W, out, {}, {}};
     if constexpr (FP8)
-        blur_fp8_tile<P, NMB, NBLK>(img, H, W, bp, scale, tiles_x, tile, 0, first);
+        blur_fp8_tile<P, NMB, NBLK, true>(img, H, W, bp, scale, tiles_x, tile, 0, first, next_of(0));
     else
-        blur_bf16_tile<P, NMB, NBLK>(img, H, W, bp, tiles_x, tile, 0, first);
+        blur_bf16_tile<P, NMB, NBLK, true>(img, H, W, bp, tiles_x, tile, 0, first, next_of(0));
     if (C == 1) return;
     WFromNetwork<NMB, NBLK, false> rest{&a, lds_w16, bias, fields2, H, W, out, {}, {}};
 #pragma unroll
@@ -613,9 +689,9 @@ __device__ __forceinline__ void fused_item(const float* img, int C, int H, int W
             for (int i = 0; i < 4; ++i) rest.wv[b][mb][i] = first.wv[b][mb][i];
     for (int c = 1; c < C; ++c) {
         if constexpr (FP8)
-            blur_fp8_tile<P, NMB, NBLK>(img, H, W, bp, scale, tiles_x, tile, c, rest);
+            blur_fp8_tile<P, NMB, NBLK, true>(img, H, W, bp, scale, tiles_x, tile, c, rest, next_of(c));
         else
-            blur_bf16_tile<P, NMB, NBLK>(img, H, W, bp, tiles_x, tile, c, rest);
+            blur_bf16_tile<P, NMB, NBLK, true>(img, H, W, bp, tiles_x, tile, c, rest, next_of(c));
     }
 }
 
@@ -627,10 +703,23 @@ __global__ void __launch_bounds__(256) blur_mlp_kernel(const float* __restrict__
                                                        const float* __restrict__ fields2, float* __restrict__ out,
                                                        int tiles_x, int tiles_y) {
     extern __shared__ uint4 lds_w16[];
-    const float* lds_bias = stage_bf16_network(lds_w16, a, wg16, bias);   // the tile's first barrier publishes them
+    constexpr int SH = TileGeom<P, NBLK>::SH;
     const int nt = tiles_x * tiles_y;
-    for (int item = blockIdx.x; item < nt; item += gridDim.x)
-        fused_item<P, NMB, NBLK, FP8>(img, C, H, W, bp, scale, a, lds_w16, lds_bias, fields2, out, tiles_x, item);
+    if ((int)blockIdx.x < nt) window_dma<SH>(stage_lds<P, NBLK>(), tile_window<P, NBLK>(img, H, W, tiles_x, blockIdx.x));
+    const float* lds_bias = stage_bf16_network(lds_w16, a, wg16, bias);   // the tile's first barrier publishes them
+    for (int item = blockIdx.x; item < nt; item += gridDim.x) {
+        const int nx = item + (int)gridDim.x;
+        const Window after = nx < nt ? tile_window<P, NBLK>(img, H, W, tiles_x, nx) : Window{};
+        fused_item<P, NMB, NBLK, FP8>(img, C, H, W, bp, scale, a, lds_w16, lds_bias, fields2, out, tiles_x, item,
+                                      after);
+    }
+}
+
+template <int P, int NMB, int NBLK, bool FP8>
+__device__ __forceinline__ Window batch_window(const FrameDesc* fr, const int* first, int n, int item) {
+    const int f = find_frame(first, n, item);
+    const FrameDesc& d = fr[f];
+    return tile_window<P, NBLK>(d.image, d.H, d.W, d.tiles_x, item - first[f]);
 }
 
 template <int P, int NMB, int NBLK, bool FP8>
@@ -639,13 +728,18 @@ __global__ void __launch_bounds__(256) blur_mlp_batch(const FrameDesc* __restric
                                                       const int* __restrict__ scale, MlpArgs a,
                                                       const uint4* __restrict__ wg16, const float* __restrict__ bias) {
     extern __shared__ uint4 lds_w16[];
-    const float* lds_bias = stage_bf16_network(lds_w16, a, wg16, bias);
+    constexpr int SH = TileGeom<P, NBLK>::SH;
     const int total = first[n];
+    if ((int)blockIdx.x < total)
+        window_dma<SH>(stage_lds<P, NBLK>(), batch_window<P, NMB, NBLK, FP8>(fr, first, n, blockIdx.x));
+    const float* lds_bias = stage_bf16_network(lds_w16, a, wg16, bias);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int f = find_frame(first, n, item);
         const FrameDesc& d = fr[f];
+        const int nx = item + (int)gridDim.x;
+        const Window after = nx < total ? batch_window<P, NMB, NBLK, FP8>(fr, first, n, nx) : Window{};
         fused_item<P, NMB, NBLK, FP8>(d.image, d.C, d.H, d.W, bp, scale, a, lds_w16, lds_bias,
-                                      d.fields + 2 * (size_t)d.H * d.W, d.blurred, d.tiles_x, item - first[f]);
+                                      d.fields + 2 * (size_t)d.H * d.W, d.blurred, d.tiles_x, item - first[f], after);
     }
 }
 
