@@ -226,6 +226,19 @@ __device__ __forceinline__ void stockham_r(int R, int N, int Ns, int lg_tpf, con
     }
 }
 
+// Between passes: a transform handled by at most 64 threads lives in one
+// wave (its LDS rows are that wave's alone), so the wave's own LDS order is
+// enough; wider transforms need the workgroup barrier.
+__device__ __forceinline__ void pass_sync(int lg_tpf) {
+    if (lg_tpf <= 6) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Whole inverse transforms of one item: the first pass gathers its inputs
 // with src (band entries or zero), the middle passes run LDS to LDS at
 // stride ld, the last pass hands every output to out(f, index, value).
@@ -240,11 +253,11 @@ __device__ __forceinline__ void ifft_item(int N, int ld, int lg_tpf, const int* 
         return [buf, ld](int f, int i) { return buf[f * ld + i]; };
     };
     stockham_r<true>(rad[0], N, 1, lg_tpf, tw, 1.0f, src, to_lds(a));
-    __syncthreads();
+    pass_sync(lg_tpf);
     int Ns = rad[0];
     for (int i = 1; i + 1 < nrad; ++i) {
         stockham_r<false>(rad[i], N, Ns, lg_tpf, tw, 1.0f, from_lds(a), to_lds(b));
-        __syncthreads();
+        pass_sync(lg_tpf);
         float2* t = a;
         a = b;
         b = t;
@@ -292,18 +305,22 @@ __device__ __forceinline__ void fields_cols_item(const FieldPlan& fp, float2* __
             twx_out[k] = make_float2((float)cs, (float)sn);
         }
     }
+    const int lg_tpf = 8 - lg_cpb;             // 256 threads
     if (fresh) {                               // first item of this frame in the workgroup
+        __syncthreads();                       // every wave done with the previous frame's tables
         fill_twiddles(tw, N);
         for (int k = threadIdx.x; k < N; k += blockDim.x) filt[k] = gauss_filter(k, N, fp.corr_len);
+        __syncthreads();
     }
-    __syncthreads();
-    const int lg_tpf = 8 - lg_cpb;             // 256 threads
-    auto noise = [&](int c, int ky) -> float2 {
-        const int j = j0 + c;
+    // this thread's column: its bin and its filter factor, once per item
+    const int jme = j0 + (int)(threadIdx.x >> lg_tpf);
+    const bool col_ok = jme < fp.Mx;
+    const int kx = band_to_bin(jme, fp.kcx, fp.Nfx, fp.Mx);
+    const float hx = col_ok ? gauss_filter(kx, fp.Nfx, fp.corr_len) * fp.norm : 0.0f;
+    auto noise = [&](int, int ky) -> float2 {
         const int kyw = ky < (N + 1) / 2 ? ky : N - ky;
-        if (j >= fp.Mx || kyw > fp.kcy) return make_float2(0.f, 0.f);
-        const int kx = band_to_bin(j, fp.kcx, fp.Nfx, fp.Mx);
-        const float h = gauss_filter(kx, fp.Nfx, fp.corr_len) * filt[ky] * fp.norm;
+        if (!col_ok || kyw > fp.kcy) return make_float2(0.f, 0.f);
+        const float h = hx * filt[ky];
         const float2 z = bin_noise(kx, ky, q, fp.k0, fp.k1);
         return make_float2(h * z.x, h * z.y);
     };
@@ -314,7 +331,7 @@ __device__ __forceinline__ void fields_cols_item(const FieldPlan& fp, float2* __
         if (y < H && j < Mx) Vq[(size_t)j * H + y] = v;
     };
     ifft_item(N, ld, lg_tpf, fp.rad_y, fp.nrad_y, tw, buf0, buf1, noise, out);
-    __syncthreads();                           // LDS free for the next item
+    if (lg_tpf > 6) __syncthreads();           // LDS free for the next item (shared rows)
 }
 
 // Row work item: plane pair q, output rows y0 .. y0 + 2^lg_rpb - 1.  The first
@@ -329,6 +346,7 @@ __device__ __forceinline__ void fields_rows_item(const FieldPlan& fp, const floa
     float2* tw = smem + 2 * rpb * ld;
     const int H = fp.H, W = fp.W, Mx = fp.Mx, kcx = fp.kcx;
     if (fresh) {                               // first item of this frame in the workgroup
+        __syncthreads();                       // every wave done with the previous frame's table
         for (int k = threadIdx.x; k < N; k += blockDim.x) tw[k] = twx[k];
         __syncthreads();
     }
@@ -351,7 +369,7 @@ __device__ __forceinline__ void fields_rows_item(const FieldPlan& fp, const floa
         if (has1) F1[(size_t)y * W + x] = s1 * v.y;
     };
     ifft_item(N, ld, 8 - lg_rpb, fp.rad_x, fp.nrad_x, tw, buf0, buf1, band, out);
-    __syncthreads();                           // LDS free for the next item
+    if (lg_rpb < 2) __syncthreads();           // LDS free for the next item (shared rows)
 }
 
 // Single frame: persistent workgroups stride over the (pair, chunk) items, so
