@@ -77,9 +77,10 @@ def traffic_from_profiles(kernel_sources):
 
 
 def copy_mode(args, torch):
-    """A plain device-to-device copy of 256 MiB, args.steps times: the bytes
-    read and written per launch are known exactly."""
-    n = 64 << 20
+    """A plain device-to-device copy of 1 GiB (larger than the last-level
+    cache), args.steps times: the bytes read and written per launch are known
+    exactly."""
+    n = 256 << 20
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(args.warmup):

@@ -384,14 +384,26 @@ __global__ void __launch_bounds__(kThreads) fields_cols_kernel(FieldPlan fp, flo
     }
 }
 
+// Row items in XCD order: workgroups go to the 8 XCDs round-robin (b on XCD
+// b % 8), so in each block of 32 slots of the persistent loop the 4 slots of
+// one XCD take 4 consecutive items; their 4 x 4 rows fill whole 128-byte
+// lines of the column-major V, which then come from that XCD's L2 instead of
+// being fetched by 4 XCDs.
+__device__ __forceinline__ int xcd_row_item(int k) { return (k & ~31) | ((k & 7) << 2) | ((k >> 3) & 3); }
+
 __global__ void __launch_bounds__(kThreads) fields_rows_kernel(FieldPlan fp, const float2* __restrict__ V,
                                                                float* __restrict__ F, int lg_rpb,
                                                                const float2* __restrict__ twx, int nchunks) {
     extern __shared__ float2 smem[];
     const int total = nchunks * fp.npairs;
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int slots = (total + 31) & ~31;
+    bool fresh = true;
+    for (int k = blockIdx.x; k < slots; k += gridDim.x) {
+        const int item = xcd_row_item(k);
+        if (item >= total) continue;
         const int q = item / nchunks;
-        fields_rows_item(fp, V, F, twx, lg_rpb, q, (item - q * nchunks) << lg_rpb, smem, item == (int)blockIdx.x);
+        fields_rows_item(fp, V, F, twx, lg_rpb, q, (item - q * nchunks) << lg_rpb, smem, fresh);
+        fresh = false;
     }
 }
 
@@ -415,8 +427,11 @@ __global__ void __launch_bounds__(kThreads) fields_rows_batch(const FrameDesc* _
                                                               const int* __restrict__ first, int n) {
     extern __shared__ float2 smem[];
     const int total = first[n];
+    const int slots = (total + 31) & ~31;
     int prev = -1;
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    for (int k = blockIdx.x; k < slots; k += gridDim.x) {
+        const int item = xcd_row_item(k);
+        if (item >= total) continue;
         const int f = find_frame(first, n, item);
         const FrameDesc& d = fr[f];
         const int l = item - first[f];
