@@ -424,12 +424,12 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
                                                                         acc[b][mb], 0, 0, 0);
             }
         };
+        fetch(0, a0, p0);                         // in flight during the network
         epi.begin(y0 + lyw, x0, g, m);           // before the accumulators are live
 #pragma unroll
         for (int b = 0; b < NBLK; ++b)
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb) acc[b][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
-        fetch(0, a0, p0);
 #pragma unroll 1
         for (int t = 0; t + 1 < T32; t += 2) {
             fetch(t + 1, a1, p1);
@@ -563,12 +563,12 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
             __builtin_amdgcn_sched_barrier(0);
         }
     };
+    load_a(0, a0);                                // in flight during the network
     epi.begin(y0 + lyw, x0, g, m);               // before the accumulators are live
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb) acc[b][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    load_a(0, a0);
 #pragma unroll 1
     for (int t = 0; t + 1 < T128; t += 2) {
         step(t, a0, a1);
