@@ -226,6 +226,39 @@ __device__ __forceinline__ void stockham_r(int R, int N, int Ns, int lg_tpf, con
     }
 }
 
+// First pass of an inverse transform whose nonzero inputs all lie in
+// x[0 .. nb) and x[N - nb .. N) (nb = N / R): only inputs r = 0 and r = R - 1
+// of a butterfly can be nonzero, so X[k] = x[j] + x[j + N - nb] e^{-2 pi i k / R}
+// (twiddles from the table, tw[k N / R]); no other input is read.
+template <int R, class Src, class Dst>
+__device__ __forceinline__ void first_pass_sparse(int N, int lg_tpf, const float2* __restrict__ tw, Src&& src,
+                                                  Dst&& dst) {
+    const int nb = N / R;
+    const int f = threadIdx.x >> lg_tpf;
+    const int tpf = 1 << lg_tpf;
+    float2 w[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) w[k] = tw[k * nb];
+    for (int j = threadIdx.x & (tpf - 1); j < nb; j += tpf) {
+        const float2 a = src(f, j), b = src(f, j + N - nb);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            dst(f, j * R + k, make_float2(a.x + b.x * w[k].x - b.y * w[k].y, a.y + b.x * w[k].y + b.y * w[k].x));
+    }
+}
+
+template <class Src, class Dst>
+__device__ __forceinline__ void first_pass_sparse_r(int R, int N, int lg_tpf, const float2* tw, Src&& src, Dst&& dst) {
+    switch (R) {
+        case 2: first_pass_sparse<2>(N, lg_tpf, tw, src, dst); break;
+        case 3: first_pass_sparse<3>(N, lg_tpf, tw, src, dst); break;
+        case 4: first_pass_sparse<4>(N, lg_tpf, tw, src, dst); break;
+        case 5: first_pass_sparse<5>(N, lg_tpf, tw, src, dst); break;
+        case 8: first_pass_sparse<8>(N, lg_tpf, tw, src, dst); break;
+        default: first_pass_sparse<9>(N, lg_tpf, tw, src, dst); break;
+    }
+}
+
 // Between passes: a transform handled by at most 64 threads lives in one
 // wave (its LDS rows are that wave's alone), so the wave's own LDS order is
 // enough; wider transforms need the workgroup barrier.
@@ -242,17 +275,23 @@ __device__ __forceinline__ void pass_sync(int lg_tpf) {
 // Whole inverse transforms of one item: the first pass gathers its inputs
 // with src (band entries or zero), the middle passes run LDS to LDS at
 // stride ld, the last pass hands every output to out(f, index, value).
-// At least two passes (N >= 72 > the largest radix).
+// At least two passes (N >= 72 > the largest radix).  band_lo / band_hi:
+// the nonzero inputs lie in [0, band_lo] and [N - band_hi, N); when both
+// parts fit in one first-pass stride the sparse first pass is used.
 template <class Src, class Out>
 __device__ __forceinline__ void ifft_item(int N, int ld, int lg_tpf, const int* rad, int nrad, const float2* tw,
-                                          float2* a, float2* b, Src&& src, Out&& out) {
+                                          float2* a, float2* b, int band_lo, int band_hi, Src&& src, Out&& out) {
     auto to_lds = [&](float2* buf) {
         return [buf, ld](int f, int i, float2 v) { buf[f * ld + i] = v; };
     };
     auto from_lds = [&](const float2* buf) {
         return [buf, ld](int f, int i) { return buf[f * ld + i]; };
     };
-    stockham_r<true>(rad[0], N, 1, lg_tpf, tw, 1.0f, src, to_lds(a));
+    const int nb0 = N / rad[0];
+    if (band_lo < nb0 && band_hi <= nb0)
+        first_pass_sparse_r(rad[0], N, lg_tpf, tw, src, to_lds(a));
+    else
+        stockham_r<true>(rad[0], N, 1, lg_tpf, tw, 1.0f, src, to_lds(a));
     pass_sync(lg_tpf);
     int Ns = rad[0];
     for (int i = 1; i + 1 < nrad; ++i) {
@@ -330,7 +369,7 @@ __device__ __forceinline__ void fields_cols_item(const FieldPlan& fp, float2* __
         const int j = j0 + c;
         if (y < H && j < Mx) Vq[(size_t)j * H + y] = v;
     };
-    ifft_item(N, ld, lg_tpf, fp.rad_y, fp.nrad_y, tw, buf0, buf1, noise, out);
+    ifft_item(N, ld, lg_tpf, fp.rad_y, fp.nrad_y, tw, buf0, buf1, fp.kcy, fp.kcy, noise, out);
     if (lg_tpf > 6) __syncthreads();           // LDS free for the next item (shared rows)
 }
 
@@ -362,13 +401,16 @@ __device__ __forceinline__ void fields_rows_item(const FieldPlan& fp, const floa
     const float s1 = has1 ? fp.sigma[p1] : 0.0f;
     float* F0 = F + (size_t)p0 * H * W;
     float* F1 = F + (size_t)p1 * H * W;
-    auto out = [&](int r, int x, float2 v) {
-        const int y = y0 + r;
-        if (y >= H || x >= W) return;
-        F0[(size_t)y * W + x] = s0 * v.x;
-        if (has1) F1[(size_t)y * W + x] = s1 * v.y;
+    // this thread's output row (the last pass hands it only its own row)
+    const int ry = y0 + (int)(threadIdx.x >> (8 - lg_rpb));
+    float* const row0 = F0 + (size_t)ry * W;
+    float* const row1 = F1 + (size_t)ry * W;
+    auto out = [&](int, int x, float2 v) {
+        if (ry >= H || x >= W) return;
+        row0[x] = s0 * v.x;
+        if (has1) row1[x] = s1 * v.y;
     };
-    ifft_item(N, ld, 8 - lg_rpb, fp.rad_x, fp.nrad_x, tw, buf0, buf1, band, out);
+    ifft_item(N, ld, 8 - lg_rpb, fp.rad_x, fp.nrad_x, tw, buf0, buf1, kcx, Mx - 1 - kcx, band, out);
     if (lg_rpb < 2) __syncthreads();           // LDS free for the next item (shared rows)
 }
 
