@@ -105,7 +105,7 @@ __device__ __forceinline__ void load_pair(PairW<NKC>& d, const uint4* __restrict
 //   B: widen its high half, both differences, pack lo.
 // The values are overwritten and lo holds a temporary between the slices,
 // so the split needs no registers beyond its source and destination.
-// Dwords from 2 zero_from on belong to a padding block: constant zero.
+// Dwords d with 2 d >= zero_from hold a padding block: constant zero.
 template <int NB, int NC, bool RELU>
 __device__ __forceinline__ void split_slice(int s, floatx4 (&v)[2][NB], int zero_from, u32x4 (&hi)[NB][NC],
                                             u32x4 (&lo)[NB][NC], int col) {
@@ -126,8 +126,8 @@ __device__ __forceinline__ void split_slice(int s, floatx4 (&v)[2][NB], int zero
         hi[nb][col][d] = pk_bf16(v[j][nb][i], v[j][nb][i + 1]);
         lo[nb][col][d] = hi[nb][col][d] << 16;
     } else {
-        // (element copies first: __builtin_bit_cast of a vector element
-        // lvalue reads element 0 with this compiler)
+        // (the elements are copied out first: __builtin_bit_cast applied to
+        // a vector element lvalue reads element 0)
         const uint32_t t0 = lo[nb][col][d], t1 = hi[nb][col][d] & 0xFFFF0000u;
         const float h0 = __builtin_bit_cast(float, t0);
         const float h1 = __builtin_bit_cast(float, t1);
