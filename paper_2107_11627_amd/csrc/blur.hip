@@ -180,6 +180,26 @@ __device__ __forceinline__ T* lds_buffer() {
     return buf;
 }
 
+constexpr int kBlurThreads = 256;   // every blur kernel runs 256-thread workgroups
+
+// f(idx) for idx = threadIdx.x + 256 i < N.  ALL: unrolled, so that the LDS
+// reads of all items are in flight together (costs registers: the fused
+// kernels have them free here, the others would spill).
+template <int N, bool ALL, class F>
+__device__ __forceinline__ void for_block_items(F&& f) {
+    if constexpr (ALL) {
+        constexpr int IT = (N + kBlurThreads - 1) / kBlurThreads;
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int idx = (int)threadIdx.x + kBlurThreads * i;
+            if (N % kBlurThreads == 0 || i + 1 < IT || idx < N) f(idx);
+        }
+    } else {
+#pragma unroll 1
+        for (int idx = threadIdx.x; idx < N; idx += kBlurThreads) f(idx);
+    }
+}
+
 // Copy a clamped (replicate-border) window of image rows y_lo.. and columns
 // x_lo.. into LDS, nr x nc floats at pitch ld; loads are issued in batches of
 // kBatch per thread before any store.
@@ -373,18 +393,18 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
             stage_window<14>(stage, SW, ic, H, W, y0 - R, x0 - R, SH, kTX + 2 * R);
             __syncthreads();
         }
-        for (int idx = threadIdx.x; idx < PH * PITCH; idx += blockDim.x) {
+        for_block_items<PH * PITCH, DMA>([&](int idx) {
             const int r = idx / PITCH, p = idx - r * PITCH;
             const float* s = stage + r * SW + p;
             const floatx8 v = {s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7]};
             rowpk[idx] = __builtin_bit_cast(uint4, to_bf16x8(v));
-        }
-        for (int idx = threadIdx.x; idx < QH * kTX; idx += blockDim.x) {
+        });
+        for_block_items<QH * kTX, DMA>([&](int idx) {
             const int r = idx / kTX, q = idx - r * kTX;
             const float* s = stage + r * SW + q + 2 * R;
             const floatx8 v = {s[0], s[SW], s[2 * SW], s[3 * SW], s[4 * SW], s[5 * SW], s[6 * SW], s[7 * SW]};
             colpk[r * CPITCH + q] = __builtin_bit_cast(uint4, to_bf16x8(v));
-        }
+        });
         __syncthreads();
         if constexpr (DMA) window_dma<SH>(stage, next);   // stage free until the next item
         floatx4 acc[NBLK][NMB];
@@ -501,14 +521,14 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
         stage_window<14>(stage8, SW, ic, H, W, y0 - R, x0 - R, SH, kTX + 2 * R);
         __syncthreads();
     }
-    for (int idx = threadIdx.x; idx < PH * PITCH; idx += blockDim.x) {
+    for_block_items<PH * PITCH, DMA>([&](int idx) {
         const int r = idx / PITCH, p = idx - r * PITCH;
         rowpk8[idx] = pack_e4m3x8(stage8 + r * SW + p, 1);
-    }
-    for (int idx = threadIdx.x; idx < QH * kTX; idx += blockDim.x) {
+    });
+    for_block_items<QH * kTX, DMA>([&](int idx) {
         const int r = idx / kTX, q = idx - r * kTX;
         colpk8[r * PITCH + q] = pack_e4m3x8(stage8 + r * SW + q + 2 * R, SW);
-    }
+    });
     __syncthreads();
     if constexpr (DMA) window_dma<SH>(stage8, next);   // stage free until the next item
     int sc[NMB];
@@ -749,7 +769,7 @@ hipError_t launch_f32(const Basis& b, const float* img, int C, int H, int W, con
     constexpr int NBLK = NMB <= 7 ? 8 : 4;
     constexpr int TY = NBLK * 2;
     const int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + TY - 1) / TY;
-    hipLaunchKernelGGL((blur_f32_kernel<NMB, NBLK>), dim3(tiles_x * tiles_y, C), dim3(256), 0, s, img, H, W, b.P,
+    hipLaunchKernelGGL((blur_f32_kernel<NMB, NBLK>), dim3(tiles_x * tiles_y, C), dim3(kBlurThreads), 0, s, img, H, W, b.P,
                        b.f32, b.t4, b.K, w, out, tiles_x);
     return hipGetLastError();
 }
@@ -763,10 +783,10 @@ hipError_t launch_lowp(const Basis& b, p2s_precision prec, const float* img, int
     const dim3 grid(tiles_x * tiles_y, C);
     if (prec == P2S_BF16) {
         constexpr int NBLK = NMB <= 7 ? 8 : 4;
-        hipLaunchKernelGGL((blur_bf16_kernel<P, NMB, NBLK>), grid, dim3(256), 0, s, img, H, W,
+        hipLaunchKernelGGL((blur_bf16_kernel<P, NMB, NBLK>), grid, dim3(kBlurThreads), 0, s, img, H, W,
                            reinterpret_cast<const uint4*>(b.bf16), b.K, w, out, tiles_x);
     } else {
-        hipLaunchKernelGGL((blur_fp8_kernel<P, NMB, 4>), grid, dim3(256), 0, s, img, H, W,
+        hipLaunchKernelGGL((blur_fp8_kernel<P, NMB, 4>), grid, dim3(kBlurThreads), 0, s, img, H, W,
                            reinterpret_cast<const uint4*>(b.fp8), b.fp8_scale, b.K, w, out, tiles_x);
     }
     return hipGetLastError();
@@ -874,14 +894,14 @@ hipError_t launch_blur_batch(const Basis& b, const BatchLaunch& bl, p2s_precisio
     const int* sc8 = b.fp8_scale;
     if (prec == P2S_FP32) {
         void* args[] = {&fr, &first, &n, &P, &bp32, &t4, &K};
-        return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(256), args, 0, s);
+        return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(kBlurThreads), args, 0, s);
     }
     if (prec == P2S_BF16) {
         void* args[] = {&fr, &first, &n, &bp16, &K};
-        return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(256), args, 0, s);
+        return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(kBlurThreads), args, 0, s);
     }
     void* args[] = {&fr, &first, &n, &bp8, &sc8, &K};
-    return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(256), args, 0, s);
+    return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(kBlurThreads), args, 0, s);
 }
 
 namespace {
@@ -1004,7 +1024,7 @@ hipError_t launch_blur_mlp(const Basis& b, const Mlp& m, p2s_precision prec, con
     const float* bias = m.bias;
     const float* fields2 = fields + 2 * (size_t)H * W;
     void* args[] = {&img, &C, &H, &W, &bp, &scale, &a, &wg16, &bias, &fields2, &out, &tiles_x, &tiles_y};
-    return hipLaunchKernel(fn, dim3(grid), dim3(256), args, network_lds_bytes(m), s);
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBlurThreads), args, network_lds_bytes(m), s);
 }
 
 hipError_t launch_blur_mlp_batch(const Basis& b, const Mlp& m, const BatchLaunch& bl, p2s_precision prec,
@@ -1028,7 +1048,7 @@ hipError_t launch_blur_mlp_batch(const Basis& b, const Mlp& m, const BatchLaunch
     const uint4* wg16 = reinterpret_cast<const uint4*>(m.w16);
     const float* bias = m.bias;
     void* args[] = {&fr, &first, &n, &bp, &scale, &a, &wg16, &bias};
-    return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(256), args, network_lds_bytes(m), s);
+    return hipLaunchKernel(fn, dim3(bl.grid[ST_BLUR]), dim3(kBlurThreads), args, network_lds_bytes(m), s);
 }
 
 hipError_t launch_blur(const Basis& b, const float* img, int C, int H, int W, const float* w, p2s_precision prec,
