@@ -79,7 +79,7 @@ __device__ __forceinline__ void epilogue(const floatx4 (&acc)[NBLK][NMB], const 
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int k = 16 * mb + 4 * g + i;
-                    part += (k < K) ? acc[b][mb][i] * wv[bb][mb][i] : 0.0f;
+                    if (k < K) part = fmaf(acc[b][mb][i], wv[bb][mb][i], part);
                 }
             part = wave_sum4(part);
             if (y < H && x < W && g == 0) out_c[(size_t)y * W + x] = part;
@@ -157,14 +157,16 @@ struct WFromNetwork {
         for (int b = 0; b < NBLK; ++b) {
             bool ok;
             const int pix = pixel(b, yw, x0, m, ok);
+            // Rows k >= K: basis and last-layer weights and biases are
+            // zero-padded, so both factors are exactly 0 there and their
+            // fused multiply-add leaves part as it is (part is never -0): the
+            // same sum, bit for bit, as the memory-reading epilogue's, which
+            // skips those rows.
             float part = 0.0f;
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int k = 16 * mb + 4 * g + i;
-                    part += (k < a->K) ? acc[b][mb][i] * wv[b][mb][i] : 0.0f;
-                }
+                for (int i = 0; i < 4; ++i) part = fmaf(acc[b][mb][i], wv[b][mb][i], part);
             part = wave_sum4(part);
             if (ok && g == 0) out_c[pix] = part;
         }
