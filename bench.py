@@ -435,6 +435,19 @@ def main():
         if not fused:
             del stages["mlp_blur"]
         res[prec]["stages_us"] = {k: float(np.mean(v)) for k, v in stages.items()}
+        if fused:
+            # the dominant kernel's average duration over back-to-back launches
+            # (one launch after lighter kernels runs faster than in steady state)
+            for _ in range(2):
+                p2s.mlp_blur(sim.net, F, NZ, img, sim.basis, prec, bl)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.stage_reps):
+                p2s.mlp_blur(sim.net, F, NZ, img, sim.basis, prec, bl)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[prec]["mlp_blur_loop_us"] = e0.elapsed_time(e1) * 1e3 / args.stage_reps
+            log(f"[bench] {prec} network+blur kernel back to back: {res[prec]['mlp_blur_loop_us']:.1f} us")
         log(f"[bench] {prec} stages (us): " + ", ".join(f"{k} {v:.1f}" for k, v in res[prec]["stages_us"].items()))
         del wbuf, fws, bl
 
@@ -444,7 +457,7 @@ def main():
 
     flops = blur_flops(C, H, W, K, P)
     nflops = mlp_flops(H, W, wl.mlp_dims)
-    fused_s = res["bf16"]["stages_us"]["mlp_blur"] * 1e-6
+    fused_s = res["bf16"]["mlp_blur_loop_us"] * 1e-6
     achieved = (flops + nflops) / fused_s / 1e12
     kernel_src = ["paper_2107_11627_amd/csrc/blur.hip", "paper_2107_11627_amd/csrc/mlp_block.hpp",
                   "paper_2107_11627_amd/csrc/internal.hpp"]
