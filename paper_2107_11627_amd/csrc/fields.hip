@@ -305,11 +305,22 @@ __device__ __forceinline__ void ifft_item(int N, int ld, int lg_tpf, const int* 
     stockham_r<false>(rad[nrad - 1], N, Ns, lg_tpf, tw, 1.0f, from_lds(a), out);
 }
 
+// tw[q] = exp(-2 pi i q / N) for q < N, each rounded once from FP64.  For
+// N divisible by 4 only the first quarter is evaluated: adding N/4 to q
+// multiplies by -i, (c, s) -> (s, -c), an exact move of the rounded values.
 __device__ void fill_twiddles(float2* tw, int N) {
-    for (int q = threadIdx.x; q < N; q += blockDim.x) {
+    const bool quarter = (N & 3) == 0;
+    const int n = quarter ? N >> 2 : N;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
         double s, c;
         sincospi(-2.0 * (double)q / (double)N, &s, &c);
-        tw[q] = make_float2((float)c, (float)s);
+        const float fc = (float)c, fs = (float)s;
+        tw[q] = make_float2(fc, fs);
+        if (quarter) {
+            tw[q + n] = make_float2(fs, -fc);
+            tw[q + 2 * n] = make_float2(-fc, -fs);
+            tw[q + 3 * n] = make_float2(-fs, fc);
+        }
     }
 }
 
@@ -337,18 +348,16 @@ __device__ __forceinline__ void fields_cols_item(const FieldPlan& fp, float2* __
     float2* buf1 = smem + cpb * ld;
     float2* tw = smem + 2 * cpb * ld;
     float* filt = reinterpret_cast<float*>(tw + N);
-    if (q == 0 && j0 == 0) {
-        for (int k = threadIdx.x; k < fp.Nfx; k += blockDim.x) {
-            double sn, cs;
-            sincospi(-2.0 * (double)k / (double)fp.Nfx, &sn, &cs);
-            twx_out[k] = make_float2((float)cs, (float)sn);
-        }
-    }
+    if (q == 0 && j0 == 0) fill_twiddles(twx_out, fp.Nfx);
     const int lg_tpf = 8 - lg_cpb;             // 256 threads
     if (fresh) {                               // first item of this frame in the workgroup
         __syncthreads();                       // every wave done with the previous frame's tables
         fill_twiddles(tw, N);
-        for (int k = threadIdx.x; k < N; k += blockDim.x) filt[k] = gauss_filter(k, N, fp.corr_len);
+        // only the band rows' factors are ever read (bins |k| <= kcy)
+        for (int i = threadIdx.x; i <= 2 * fp.kcy; i += blockDim.x) {
+            const int k = i <= fp.kcy ? i : N - (i - fp.kcy);
+            filt[k] = gauss_filter(k, N, fp.corr_len);
+        }
         __syncthreads();
     }
     // this thread's column: its bin and its filter factor, once per item
