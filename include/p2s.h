@@ -196,6 +196,26 @@ int p2s_simulate(const float* image, int C, int H, int W, double D_over_r0, int 
                  p2s_basis_t basis, p2s_mlp_t mlp, uint64_t seed, p2s_precision precision,
                  const p2s_params* params, float* out, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * frame as p2s_simulate, bit for bit, with the intermediates in a device
+ * array of P2S_NOALLOC_SCRATCH_BYTES that the library holds per GPU until the
+ * process ends, instead of a caller workspace.  No allocation happens in the
+ * call.  The frame needs, each rounded up to 256 bytes: the fields
+ * (4 n_zernike H W bytes), the field generator's intermediate (part of
+ * p2s_fields_workspace_bytes) or, when the network and blur run as two
+ * kernels (P2S_FP32, or a network the fused kernel cannot hold), the larger
+ * of it and the weights w (4 H W K bytes), and the blurred image (4 C H W
+ * bytes); EINVAL when that exceeds the scratch (a 512 x 512 frame of up to 3
+ * channels fits in every precision).  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads) race
+ * and give undefined results; order them on one stream.  Arguments as in
+ * p2s_simulate. */
+#define P2S_NOALLOC_SCRATCH_BYTES ((size_t)160 << 20)
+int p2s_simulate_noalloc(const float* image, int C, int H, int W, double D_over_r0, int n_zernike,
+                         p2s_basis_t basis, p2s_mlp_t mlp, uint64_t seed, p2s_precision precision,
+                         const p2s_params* params, float* out, void* stream);
+
 /* ------------------------------------------------------------- batches --
  * Many frames, of any sizes and channel counts, through the same four stages
  * as p2s_simulate, with one launch per stage for the whole batch: every

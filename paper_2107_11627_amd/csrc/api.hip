@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -423,12 +424,15 @@ struct SimLayout {
     size_t fields, region2, blurred, total;
 };
 
-SimLayout sim_layout(int C, int H, int W, int nz, int K, const Params& pr) {
+// with_w: the second region also holds the network output w (the path that
+// runs the network and the blur as two kernels); without it, only the field
+// generator's intermediate.
+SimLayout sim_layout(int C, int H, int W, int nz, int K, const Params& pr, bool with_w = true) {
     SimLayout L;
     const size_t HW = (size_t)H * W;
     L.fields = 0;
     const size_t fb = align256((size_t)nz * HW * 4);
-    const size_t r2 = std::max(fields_ws(H, W, nz, pr), align256(HW * K * 4));
+    const size_t r2 = with_w ? std::max(fields_ws(H, W, nz, pr), align256(HW * K * 4)) : fields_ws(H, W, nz, pr);
     L.region2 = fb;
     L.blurred = fb + r2;
     L.total = L.blurred + align256((size_t)C * HW * 4);
@@ -690,6 +694,112 @@ uint16_t f32_to_bf16_rne(float x) {
 
 }  // namespace p2s
 
+namespace p2s {
+namespace {
+
+// Intermediates of the allocation-free entry point: a file-scope device array
+// (one copy per GPU, allocated when the code object loads and held until the
+// process ends).  In host code `scratch` only names the symbol; its device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current.
+constexpr size_t kScratchBytes = P2S_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+int scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(P2S_EUNSUPPORTED, "device ordinal %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress of the device scratch");
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return P2S_OK;
+}
+
+}  // namespace
+}  // namespace p2s
+
+namespace p2s {
+namespace {
+
+// One frame through the four stages on stream s.  ws == nullptr: the
+// intermediates go to the device scratch array (sized for the path that runs,
+// EINVAL when it is too small); otherwise to the caller's workspace, which
+// must hold p2s_workspace_bytes.
+int simulate_impl(const float* image, int C, int H, int W, double D_over_r0, int n_zernike, p2s_basis_t basis,
+                  p2s_mlp_t mlp, uint64_t seed, p2s_precision precision, const p2s_params* params, float* out,
+                  void* ws, size_t ws_bytes, bool use_scratch, hipStream_t s) {
+    Params pr;
+    int rc = read_params(params, &pr);
+    if (rc) return rc;
+    if (!basis || !mlp) return fail(P2S_EINVAL, "basis or mlp is NULL");
+    rc = check_frame(C, H, W);
+    if (rc) return rc;
+    rc = check_prec(precision);
+    if (rc) return rc;
+    if (n_zernike < 3 || n_zernike > P2S_MAX_ZERNIKE)
+        return fail(P2S_EINVAL, "n_zernike must be in [3, %d], got %d", P2S_MAX_ZERNIKE, n_zernike);
+    if (mlp->m.dims[0] != n_zernike - 2)
+        return fail(P2S_EINVAL, "n_zernike - 2 = %d does not match the network input width %d", n_zernike - 2,
+                    mlp->m.dims[0]);
+    if (mlp->m.dims[mlp->m.L] != basis->b.K)
+        return fail(P2S_EINVAL, "network output width %d does not match the basis size K = %d",
+                    mlp->m.dims[mlp->m.L], basis->b.K);
+    if (precision != P2S_FP32 && !basis->b.bf16_ok)
+        return fail(P2S_EUNSUPPORTED, "BF16 and FP8 blur need a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", basis->b.P);
+    if (!image || !out || (!use_scratch && !ws)) return fail(P2S_EINVAL, "image, out or workspace is NULL");
+    if (!(std::isfinite(D_over_r0) && D_over_r0 >= 0.0)) return fail(P2S_EINVAL, "D/r0 must be finite and >= 0");
+    const int Nfy = grid_of(H, pr.corr_len), Nfx = grid_of(W, pr.corr_len);
+    if (Nfy > kMaxFftLen || Nfx > kMaxFftLen)
+        return fail(P2S_EUNSUPPORTED, "noise grid %d x %d exceeds the single-workgroup FFT limit %d", Nfy, Nfx, kMaxFftLen);
+    const bool fused = blur_mlp_supported(basis->b, mlp->m, precision);
+    const SimLayout L = sim_layout(C, H, W, n_zernike, basis->b.K, pr, !use_scratch || !fused);
+    if (use_scratch) {
+        if (L.total > kScratchBytes)
+            return fail(P2S_EINVAL, "frame needs %zu bytes of intermediates, more than the %zu-byte device scratch",
+                        L.total, kScratchBytes);
+        rc = scratch_address(&ws);
+        if (rc) return rc;
+        ws_bytes = kScratchBytes;
+    } else if (ws_bytes < L.total) {
+        return fail(P2S_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    }
+    const size_t n = (size_t)C * H * W * 4;
+    if (overlap(image, n, out, n)) return fail(P2S_EINVAL, "image and out overlap");
+    if (overlap(ws, L.total, out, n) || overlap(ws, L.total, image, n))
+        return fail(P2S_EINVAL, "workspace overlaps image or out");
+    char* base = (char*)ws;
+    float* F = (float*)(base + L.fields);
+    float* r2 = (float*)(base + L.region2);
+    float* bl = (float*)(base + L.blurred);
+    rc = make_fields_impl(H, W, D_over_r0, n_zernike, seed, pr, F, r2, L.blurred - L.region2, s);
+    if (rc) return rc;
+    if (fused) {     // w never leaves the chip
+        hipError_t e = launch_blur_mlp(basis->b, mlp->m, precision, image, C, H, W, F, bl, s);
+        if (e != hipSuccess) return hip_fail(e, "fused network and blur kernel");
+    } else {
+        rc = mlp_impl(mlp->m, F, n_zernike, H, W, precision, r2, s);
+        if (rc) return rc;
+        rc = blur_impl(image, C, H, W, basis->b, r2, precision, bl, s);
+        if (rc) return rc;
+    }
+    rc = warp_impl(bl, C, H, W, F, pr, out, s);
+    if (rc) return rc;
+    return ok();
+}
+
+}  // namespace
+}  // namespace p2s
+
 struct p2s_batch_s {
     p2s::BatchHost* h;
 };
@@ -886,54 +996,15 @@ int p2s_warp(const float* in, int C, int H, int W, const float* tilt, const p2s_
 int p2s_simulate(const float* image, int C, int H, int W, double D_over_r0, int n_zernike, p2s_basis_t basis,
                  p2s_mlp_t mlp, uint64_t seed, p2s_precision precision, const p2s_params* params, float* out,
                  void* ws, size_t ws_bytes, void* stream) {
-    Params pr;
-    int rc = read_params(params, &pr);
-    if (rc) return rc;
-    if (!basis || !mlp) return fail(P2S_EINVAL, "basis or mlp is NULL");
-    rc = check_frame(C, H, W);
-    if (rc) return rc;
-    rc = check_prec(precision);
-    if (rc) return rc;
-    if (n_zernike < 3 || n_zernike > P2S_MAX_ZERNIKE)
-        return fail(P2S_EINVAL, "n_zernike must be in [3, %d], got %d", P2S_MAX_ZERNIKE, n_zernike);
-    if (mlp->m.dims[0] != n_zernike - 2)
-        return fail(P2S_EINVAL, "n_zernike - 2 = %d does not match the network input width %d", n_zernike - 2,
-                    mlp->m.dims[0]);
-    if (mlp->m.dims[mlp->m.L] != basis->b.K)
-        return fail(P2S_EINVAL, "network output width %d does not match the basis size K = %d",
-                    mlp->m.dims[mlp->m.L], basis->b.K);
-    if (precision != P2S_FP32 && !basis->b.bf16_ok)
-        return fail(P2S_EUNSUPPORTED, "BF16 and FP8 blur need a PSF side P = 8a + 1 (9, 17, 25, 33); got %d", basis->b.P);
-    if (!image || !out || !ws) return fail(P2S_EINVAL, "image, out or workspace is NULL");
-    if (!(std::isfinite(D_over_r0) && D_over_r0 >= 0.0)) return fail(P2S_EINVAL, "D/r0 must be finite and >= 0");
-    const int Nfy = grid_of(H, pr.corr_len), Nfx = grid_of(W, pr.corr_len);
-    if (Nfy > kMaxFftLen || Nfx > kMaxFftLen)
-        return fail(P2S_EUNSUPPORTED, "noise grid %d x %d exceeds the single-workgroup FFT limit %d", Nfy, Nfx, kMaxFftLen);
-    const SimLayout L = sim_layout(C, H, W, n_zernike, basis->b.K, pr);
-    if (ws_bytes < L.total) return fail(P2S_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
-    const size_t n = (size_t)C * H * W * 4;
-    if (overlap(image, n, out, n)) return fail(P2S_EINVAL, "image and out overlap");
-    if (overlap(ws, L.total, out, n) || overlap(ws, L.total, image, n))
-        return fail(P2S_EINVAL, "workspace overlaps image or out");
-    hipStream_t s = (hipStream_t)stream;
-    char* base = (char*)ws;
-    float* F = (float*)(base + L.fields);
-    float* r2 = (float*)(base + L.region2);
-    float* bl = (float*)(base + L.blurred);
-    rc = make_fields_impl(H, W, D_over_r0, n_zernike, seed, pr, F, r2, L.blurred - L.region2, s);
-    if (rc) return rc;
-    if (blur_mlp_supported(basis->b, mlp->m, precision)) {     // w never leaves the chip
-        hipError_t e = launch_blur_mlp(basis->b, mlp->m, precision, image, C, H, W, F, bl, s);
-        if (e != hipSuccess) return hip_fail(e, "fused network and blur kernel");
-    } else {
-        rc = mlp_impl(mlp->m, F, n_zernike, H, W, precision, r2, s);
-        if (rc) return rc;
-        rc = blur_impl(image, C, H, W, basis->b, r2, precision, bl, s);
-        if (rc) return rc;
-    }
-    rc = warp_impl(bl, C, H, W, F, pr, out, s);
-    if (rc) return rc;
-    return ok();
+    return simulate_impl(image, C, H, W, D_over_r0, n_zernike, basis, mlp, seed, precision, params, out, ws,
+                         ws_bytes, false, (hipStream_t)stream);
+}
+
+int p2s_simulate_noalloc(const float* image, int C, int H, int W, double D_over_r0, int n_zernike,
+                         p2s_basis_t basis, p2s_mlp_t mlp, uint64_t seed, p2s_precision precision,
+                         const p2s_params* params, float* out, void* stream) {
+    return simulate_impl(image, C, H, W, D_over_r0, n_zernike, basis, mlp, seed, precision, params, out, nullptr,
+                         0, true, (hipStream_t)stream);
 }
 
 size_t p2s_batch_workspace_bytes(const p2s_frame* frames, int n, int n_zernike, int K, const p2s_params* params) {

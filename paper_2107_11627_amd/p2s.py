@@ -28,6 +28,7 @@ EXPORTS = [
     "p2s_mlp_info", "p2s_make_fields", "p2s_mlp", "p2s_blur", "p2s_mlp_blur", "p2s_warp",
     "p2s_simulate", "p2s_debug_noise", "p2s_batch_workspace_bytes", "p2s_batch_create",
     "p2s_batch_upload", "p2s_batch_launch", "p2s_batch_info", "p2s_batch_destroy", "p2s_simulate_batch",
+    "p2s_simulate_noalloc",
 ]
 
 
@@ -85,6 +86,7 @@ def lib():
         L.p2s_mlp_blur.argtypes = [vp, vp, i, vp, i, i, i, vp, i, vp, vp]
         L.p2s_warp.argtypes = [vp, i, i, i, vp, vp, vp, vp]
         L.p2s_simulate.argtypes = [vp, i, i, i, d, i, vp, vp, u64, i, vp, vp, vp, sz, vp]
+        L.p2s_simulate_noalloc.argtypes = [vp, i, i, i, d, i, vp, vp, u64, i, vp, vp, vp]
         L.p2s_debug_noise.argtypes = [i, i, i, u64, vp, vp, vp]
         L.p2s_batch_workspace_bytes.argtypes = [vp, i, i, i, vp]
         L.p2s_batch_workspace_bytes.restype = sz
@@ -272,6 +274,18 @@ def simulate(image, d_over_r0, basis: Basis, net: Mlp, seed, precision, out, ws,
                               basis.handle, net.handle, int(seed) & (2 ** 64 - 1), _prec(precision),
                               _params(corr_len_px, q_sampling), _ptr(out, torch.float32, (C_, H, W), "out"),
                               _ptr(ws, name="ws"), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def simulate_noalloc(image, d_over_r0, basis: Basis, net: Mlp, seed, precision, out, n_zernike=35,
+                     corr_len_px=16.0, q_sampling=2.0, stream=None):
+    """p2s_simulate with the intermediates in the library's device scratch
+    (no workspace, no allocation); calls on one GPU must not overlap."""
+    import torch
+    C_, H, W = image.shape
+    _check(lib().p2s_simulate_noalloc(_ptr(image, torch.float32, None, "image"), C_, H, W, float(d_over_r0),
+                                      n_zernike, basis.handle, net.handle, int(seed) & (2 ** 64 - 1),
+                                      _prec(precision), _params(corr_len_px, q_sampling),
+                                      _ptr(out, torch.float32, (C_, H, W), "out"), _stream(stream)))
 
 
 def debug_noise(Nfy, Nfx, pair, seed, raw, normals=None, stream=None):
