@@ -189,12 +189,28 @@ def batch_section(args, torch, p2s, S, pbasis):
         outs = [torch.empty_like(im) for im in imgs]
         ws = sim.batch_workspace(shapes)
         rec = {"frames": len(imgs), "megapixels_x_channels": mpix, "workspace_GiB": ws.numel() / 2 ** 30}
-        # one sampled frame (the smallest): its outputs are kept for the CPU
-        # baseline leg, which compares them with the FP64 oracle
-        ks = min(range(len(imgs)), key=lambda i: shapes[i][0] * shapes[i][1] * shapes[i][2])
-        rec["oracle_sample"] = {"frame": ks, "shape": list(shapes[ks])}
-        samples[name] = {"image": imgs[ks].cpu().numpy(), "d": dd[ks], "seed": seeds[ks], "basis": basis,
-                         "Ws": Ws, "bs": bs, "out": {}}
+        # frames kept for the oracle check in the CPU-baseline leg: the first 4
+        # of the uniform batch; 8 of the ragged batch, one of each size and
+        # channel count in order of appearance, starting with a 768 x 768 RGB one
+        if name == "batch256":
+            pick = list(range(4))
+        else:
+            first768 = next(i for i, sh in enumerate(shapes) if sh == (3, 768, 768))
+            pick, seen = [first768], {shapes[first768]}
+            for i, sh in enumerate(shapes):
+                if len(pick) == 8:
+                    break
+                if sh not in seen:
+                    pick.append(i)
+                    seen.add(sh)
+            for i in range(len(shapes)):
+                if len(pick) == 8:
+                    break
+                if i not in pick:
+                    pick.append(i)
+        rec["oracle_frames"] = [{"frame": i, "shape": list(shapes[i])} for i in pick]
+        samples[name] = [{"image": imgs[i].cpu().numpy(), "d": dd[i], "seed": seeds[i], "out": {}} for i in pick]
+        samples[name + "_basis"] = (basis, Ws, bs)
         for prec in ("bf16", "fp32", "fp8"):
             opt = autotune.tune(sim, imgs, dd, seeds, prec, outs=outs, ws=ws)
             b = p2s.Batch(imgs, outs, dd, seeds, sim.basis, sim.net, prec, ws, sim.n_zernike, **opt)
@@ -219,7 +235,8 @@ def batch_section(args, torch, p2s, S, pbasis):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / reps
             items, grid = b.info()
-            samples[name]["out"][prec] = outs[ks].cpu().numpy().astype(np.float64)
+            for smp, i in zip(samples[name], pick):
+                smp["out"][prec] = outs[i].cpu().numpy().astype(np.float64)
             # the same frames one at a time through p2s_simulate (one untimed pass
             # first, so that the workspace has reached its largest size)
             for k, im in enumerate(imgs):
@@ -249,11 +266,14 @@ def batch_section(args, torch, p2s, S, pbasis):
 
 
 def serving_section(args, torch, p2s, S, pbasis):
-    """The serving workload: requests of 128..2048 RGB arrive as a Poisson
-    process at a fixed rate; the continuous-batching loop runs them in BF16
-    under the HBM admission budget.  Also: the same requests all queued at
-    once (saturated throughput), and the plain FP32 per-frame path (one
-    p2s_simulate call per request, in arrival order)."""
+    """The serving workload: requests of 128..2048 RGB through the
+    continuous-batching loop in BF16 under the HBM admission budget.  First
+    all requests queued at once (the saturated request rate), then Poisson
+    arrivals at a fixed fraction of that rate (latency p50/p99, on the host
+    clock), then the plain FP32 per-frame path (one p2s_simulate call per
+    request).  Request images and outputs are allocated before the loop runs;
+    the loop itself allocates only its arena (the budget).  A few served
+    requests are kept for the oracle check in the CPU-baseline leg."""
     from paper_2107_11627_amd import serving as sv
 
     wl = S.workload("serving")
@@ -264,38 +284,72 @@ def serving_section(args, torch, p2s, S, pbasis):
     frames = wl.frames[: args.serving_requests]
     t0 = time.perf_counter()
     imgs = [S.blob_image_device(f.H, f.W, f.C, f.image_seed, f.noise_std, device_noise=True) for f in frames]
+    outs = [torch.empty_like(im) for im in imgs]
     torch.cuda.synchronize()
     log(f"[bench] serving: {len(imgs)} request images on the device in {time.perf_counter() - t0:.1f} s")
-    rate = wl.extra["arrival_rate_hz"]
     budget = wl.extra["hbm_budget_bytes"]
-    arr = sv.poisson_arrivals(len(frames), rate, wl.extra["arrival_seed"])
 
     def requests(arrivals):
-        return [sv.Request(i, imgs[i], f.d_over_r0, f.field_seed, float(arrivals[i])) for i, f in enumerate(frames)]
+        rs = []
+        for i, f in enumerate(frames):
+            r = sv.Request(i, imgs[i], f.d_over_r0, f.field_seed, float(arrivals[i]))
+            r.out = outs[i]
+            rs.append(r)
+        return rs
 
-    res = {"requests": len(frames), "arrival_rate_hz": rate, "budget_GiB": budget / 2 ** 30,
-           "megapixels_x_channels": sum(f.C * f.H * f.W for f in frames) / 1e6}
-    for label, arrivals in (("poisson", arr), ("saturated", np.zeros(len(frames)))):
+    res = {"requests": len(frames), "budget_GiB": budget / 2 ** 30,
+           "megapixels_x_channels": sum(f.C * f.H * f.W for f in frames) / 1e6,
+           "clock": "host perf_counter for arrivals and finishes (finish = first poll that sees the batch's event)"}
+
+    def run(label, arrivals):
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
         ex = sv.GpuExecutor(sim, "bf16", budget, n_slots=args.serving_slots)
         eng = sv.Engine(ex, budget, n_slots=args.serving_slots, max_batch_frames=args.serving_max_batch)
-        # warm the kernels and the plan path once on a few requests
-        sv.run(eng, requests(np.zeros(len(frames)))[:4])
+        sv.run(eng, requests(np.zeros(len(frames)))[:4])          # warm the kernels and the plan path
         eng = sv.Engine(ex, budget, n_slots=args.serving_slots, max_batch_frames=args.serving_max_batch)
         st = sv.run(eng, requests(arrivals))
+        torch.cuda.synchronize()
+        st["device_bytes_allocated_by_loop"] = torch.cuda.max_memory_allocated() - base   # the arena
         res[label] = st
         log(f"[bench] serving {label}: {st['frames_per_s']:.1f} frames/s, p50 {st['latency_ms']['p50']:.2f} ms, "
-            f"p99 {st['latency_ms']['p99']:.2f} ms, {st['batches']} batches (mean {st['mean_batch_frames']:.1f} "
-            f"frames), peak {st['peak_hbm_bytes'] / 2 ** 30:.1f} GiB")
+            f"p99 {st['latency_ms']['p99']:.2f} ms, {st['batches']} batches (mean {st['mean_batch_frames']:.2f} "
+            f"frames, {st['overlapped_launches']} overlapped), peak {st['peak_hbm_bytes'] / 2 ** 30:.1f} GiB")
         del ex, eng
-        torch.cuda.empty_cache()
+
+    run("saturated", np.zeros(len(frames)))
+    frac = wl.extra["load_fraction"]
+    rate = frac * res["saturated"]["frames_per_s"]
+    res["arrival_rate_hz"] = rate
+    res["load_fraction_of_saturated"] = frac
+    run("poisson", sv.poisson_arrivals(len(frames), rate, wl.extra["arrival_seed"]))
+    # oracle sample: 7 early requests and the largest one
+    pick = list(range(min(7, len(frames))))
+    big = max(range(len(frames)), key=lambda i: frames[i].H * frames[i].W)
+    if big not in pick:
+        pick.append(big)
+    samples = [{"rid": i, "image": imgs[i].cpu().numpy(), "d": frames[i].d_over_r0, "seed": frames[i].field_seed,
+                "out": {"bf16": outs[i].cpu().numpy().astype(np.float64)}} for i in pick]
+    # one 2048 x 2048 RGB request through the same loop on its own
+    f2 = S.FrameSpec(2048, 2048, 3, 4.0, 7999, 3999, 0.02)
+    im2 = S.blob_image_device(f2.H, f2.W, f2.C, f2.image_seed, f2.noise_std, device_noise=True)
+    r2 = sv.Request(0, im2, f2.d_over_r0, f2.field_seed, 0.0)
+    r2.out = torch.empty_like(im2)
+    ex = sv.GpuExecutor(sim, "bf16", budget, n_slots=1)
+    st2 = sv.run(sv.Engine(ex, budget, n_slots=1), [r2])
+    torch.cuda.synchronize()
+    res["single_2048_rgb_latency_ms"] = st2["latency_ms"]["p50"]
+    samples.append({"rid": "2048x2048", "image": im2.cpu().numpy(), "d": f2.d_over_r0, "seed": f2.field_seed,
+                    "out": {"bf16": r2.out.cpu().numpy().astype(np.float64)}})
+    del ex, im2, r2
     # plain FP32 per-frame path over the same requests
     lat = []
-    out = None
     t = time.perf_counter()
     for i, im in enumerate(imgs):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        out = sim(im, frames[i].d_over_r0, frames[i].field_seed, "fp32")
+        sim(im, frames[i].d_over_r0, frames[i].field_seed, "fp32", out=outs[i])
         b.record()
         lat.append((a, b))
     torch.cuda.synchronize()
@@ -306,9 +360,30 @@ def serving_section(args, torch, p2s, S, pbasis):
                              "note": "device time per p2s_simulate call, frames back to back"}
     res["bf16_serving_vs_fp32_per_frame"] = res["saturated"]["frames_per_s"] / res["fp32_per_frame"]["frames_per_s"]
     log(f"[bench] serving fp32 per-frame: {res['fp32_per_frame']['frames_per_s']:.1f} frames/s")
-    del imgs, out
+    del imgs, outs
     torch.cuda.empty_cache()
-    return res
+    return res, {"basis": basis, "Ws": Ws, "bs": bs, "requests": samples}
+
+
+def oracle_error(smp, basis, Ws, bs, n_pix, seed):
+    """Relative L2 error of a GPU output against the FP64 oracle: the whole
+    frame when it is small, else on n_pix sampled pixels (corners, edge
+    midpoints and uniform draws) evaluated one by one."""
+    from oracle.simulate import simulate as osimulate
+    from oracle.simulate import simulate_pixels as osimulate_pixels
+    img = smp["image"]
+    C, H, W = img.shape
+    if H * W <= 512 * 320:
+        ref = osimulate(img, smp["d"], basis, Ws, bs, seed=smp["seed"])["out"]
+        return {p: float(np.linalg.norm(got - ref) / np.linalg.norm(ref)) for p, got in smp["out"].items()}, "whole"
+    rng = np.random.default_rng(seed)
+    pix = [(c, y, x) for c in range(C) for y in (0, H // 2, H - 1) for x in (0, W // 2, W - 1)]
+    while len(pix) < n_pix:
+        pix.append((int(rng.integers(C)), int(rng.integers(H)), int(rng.integers(W))))
+    ref = osimulate_pixels(img, smp["d"], basis, Ws, bs, smp["seed"], pix)
+    idx = tuple(np.array(pix).T)
+    return ({p: float(np.linalg.norm(got[idx] - ref) / np.linalg.norm(ref)) for p, got in smp["out"].items()},
+            f"{len(pix)} sampled pixels")
 
 
 def main():
@@ -480,7 +555,7 @@ def main():
                 "note": "the network's share runs on BF16 MFMA (peak 2500)"}
 
     batches, batch_samples = (None, {}) if args.no_batches else batch_section(args, torch, p2s, S, pbasis)
-    serving = None if args.no_serving else serving_section(args, torch, p2s, S, pbasis)
+    serving, serving_samples = (None, None) if args.no_serving else serving_section(args, torch, p2s, S, pbasis)
 
     cpu = None
     errs = None
@@ -503,11 +578,32 @@ def main():
                "sample": f"{args.cpu_frames} whole single512 frames (fields, network, blur, warp) in FP64 NumPy",
                "host_cpus": os.cpu_count()}
         errs = {p: float(np.linalg.norm(outs[p] - ref) / np.linalg.norm(ref)) for p in outs}
-        # the sampled frame of each batch workload, every precision, against the oracle
-        for name, smp in batch_samples.items():
-            r = osimulate(smp["image"], smp["d"], smp["basis"], smp["Ws"], smp["bs"], seed=smp["seed"])["out"]
-            for p, got in smp["out"].items():
-                batches[name]["oracle_sample"][p] = float(np.linalg.norm(got - r) / np.linalg.norm(r))
+        # the kept frames of each batch workload and served requests, every
+        # precision they ran in, against the oracle (parity checks; untimed)
+        t1 = time.perf_counter()
+        for name in ("batch256", "ragged"):
+            if name not in batch_samples:
+                continue
+            ob, oW, ob_ = batch_samples[name + "_basis"]
+            for k, smp in enumerate(batch_samples[name]):
+                e, how = oracle_error(smp, ob, oW, ob_, 4000, k)
+                batches[name]["oracle_frames"][k].update({"rel_l2": e, "compared_on": how})
+            worst = {p: max(f["rel_l2"][p] for f in batches[name]["oracle_frames"]) for p in ("fp32", "bf16", "fp8")}
+            batches[name]["oracle_worst_rel_l2"] = worst
+            log(f"[bench] {name}: worst rel-L2 vs oracle over {len(batch_samples[name])} frames: " +
+                ", ".join(f"{p} {v:.2e}" for p, v in worst.items()))
+        if serving_samples:
+            checked = []
+            for k, smp in enumerate(serving_samples["requests"]):
+                e, how = oracle_error(smp, serving_samples["basis"], serving_samples["Ws"], serving_samples["bs"],
+                                      4000, 100 + k)
+                checked.append({"request": smp["rid"], "shape": list(smp["image"].shape), "rel_l2_bf16": e["bf16"],
+                                "compared_on": how})
+            serving["oracle_requests"] = checked
+            serving["oracle_worst_rel_l2_bf16"] = max(c["rel_l2_bf16"] for c in checked)
+            log(f"[bench] serving: worst BF16 rel-L2 vs oracle over {len(checked)} requests: "
+                f"{serving['oracle_worst_rel_l2_bf16']:.2e}")
+        log(f"[bench] oracle parity checks of batches and serving took {time.perf_counter() - t1:.1f} s")
         log(f"[bench] oracle {cpu['value']:.3f} frames/s; rel-L2 vs oracle: " +
             ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
 

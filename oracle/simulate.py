@@ -48,3 +48,51 @@ def simulate(image: np.ndarray, d_over_r0: float, basis: np.ndarray, Ws=None, bs
         res["exact_blurred"] = ex
         res["exact_out"] = np.stack([warp.tilt_warp(ex[c], F[0], F[1], q) for c in range(C)])
     return res
+
+
+def simulate_pixels(image: np.ndarray, d_over_r0: float, basis: np.ndarray, Ws, bs, seed: int, pixels,
+                    n_zernike: int = 35, corr_len: float = 16.0, q: float = 2.0) -> np.ndarray:
+    """simulate()["out"] at chosen output pixels only, for frames too large
+    to blur whole on the host.  The same steps, evaluated where they are
+    needed: the fields in full; then for each output pixel (c, y, x) its tilt
+    sample position (Sec. 2.2; clamped, bilinear as in ``warp``) and, at each
+    of the four blurred pixels that sample reads, the network on that pixel's
+    alpha_4.. (Sec. 3.3) dotted with the K convolutions there (Eq. 5: taps
+    b_k[i][j] at offset (i - R, j - R), replicate border).  pixels: sequence
+    of (c, y, x); returns float64 [len(pixels)].
+
+    Parity: pinned against simulate() at every pixel of small frames."""
+    img = np.asarray(image, dtype=np.float64)
+    if img.ndim == 2:
+        img = img[None]
+    C, H, W = img.shape
+    K, P, _ = basis.shape
+    R = (P - 1) // 2
+    B = np.asarray(basis, dtype=np.float64)
+    F = fields.make_fields(H, W, d_over_r0, n_zernike, seed, corr_len)
+    dx = warp.displacement(F[0], q)
+    dy = warp.displacement(F[1], q)
+    offs = np.arange(P) - R
+    blurred = {}
+
+    def blurred_at(c, y, x):
+        if (c, y, x) not in blurred:
+            w = mlp.forward(Ws, bs, F[2:, y, x][None, :])[0]                   # [K]
+            ys = np.clip(y - offs, 0, H - 1)                                   # I(y - (i - R))
+            xs = np.clip(x - offs, 0, W - 1)
+            patch = img[c][np.ix_(ys, xs)]                                     # patch[i][j]
+            conv = np.tensordot(B, patch, axes=([1, 2], [0, 1]))               # b_k conv I at (y, x)
+            blurred[(c, y, x)] = float(np.dot(w, conv))
+        return blurred[(c, y, x)]
+
+    out = np.empty(len(pixels), dtype=np.float64)
+    for n, (c, y, x) in enumerate(pixels):
+        sx = min(max(x + dx[y, x], 0.0), W - 1.0)
+        sy = min(max(y + dy[y, x], 0.0), H - 1.0)
+        x0, y0 = int(np.floor(sx)), int(np.floor(sy))
+        x1, y1 = min(x0 + 1, W - 1), min(y0 + 1, H - 1)
+        fx, fy = sx - x0, sy - y0
+        top = (1.0 - fx) * blurred_at(c, y0, x0) + fx * blurred_at(c, y0, x1)
+        bot = (1.0 - fx) * blurred_at(c, y1, x0) + fx * blurred_at(c, y1, x1)
+        out[n] = (1.0 - fy) * top + fy * bot
+    return out

@@ -14,8 +14,9 @@ in the design notes):
 * ``single512``  512x512 C=1, D/r0=3, K=100 basis of 33x33, MLP 33-100-100-100.
 * ``batch256``   64 frames 256x256 RGB, D/r0 ~ U[1,4].
 * ``ragged``     200 frames, sizes from a fixed set, C in {1,3}, D/r0 ~ U[0.5,5].
-* ``serving``    1000 requests, Poisson arrivals at 250/s, sizes 128..2048
-                 (multiples of 64), RGB, admission budget 32 GiB.
+* ``serving``    1000 requests, sizes 128..2048 (multiples of 64), RGB,
+                 admission budget 32 GiB; Poisson arrivals at 70 % of the
+                 saturated request rate measured in the same run.
 """
 from __future__ import annotations
 
@@ -224,7 +225,7 @@ def workload(name: str) -> Workload:
         d = rng.uniform(0.5, 6.0, n)
         fr = [FrameSpec(int(hs[i]), int(ws[i]), 3, float(d[i]), 7000 + i, 3000 + i, 0.02)
               for i in range(n)]
-        return Workload(name, fr, extra={"arrival_seed": 41, "arrival_rate_hz": 250.0,
+        return Workload(name, fr, extra={"arrival_seed": 41, "load_fraction": 0.7,
                                          "hbm_budget_bytes": 32 << 30}, **shared)
     raise KeyError(name)
 

@@ -14,8 +14,17 @@ admits queued requests first come, first served whenever
 
 It never waits to fill a batch: whatever is queued and fits goes out as soon as
 a slot frees up.  A request whose frame alone cannot fit the budget is
-rejected.  Latency is finish time minus arrival time, finish times taken from
-device events.
+rejected.  A batch whose launch fails (for example an allocation or launch
+error from the library) fails only its own requests: their arena block is
+returned and the loop keeps serving the others.
+
+Images and outputs are the caller's device buffers, as in the C ABI; the
+budget bounds what the engine itself holds on the device (the arena with the
+plans and intermediates of the batches in flight) plus any output bytes an
+executor reports for outputs it allocates itself.
+
+Latency is finish time minus arrival time, both on the engine's host clock:
+a batch counts as finished at the first poll that sees its completion event.
 
 The engine talks to an executor (launch a batch on a slot, ask whether it has
 finished, release it), so that the host logic runs unchanged against a fake
@@ -89,6 +98,8 @@ class Request:
     finished: Optional[float] = None
     batch_id: Optional[int] = None
     rejected: bool = False
+    failed: bool = False
+    error: Optional[str] = None
 
     @property
     def latency(self) -> Optional[float]:
@@ -125,6 +136,7 @@ class Engine:
         self.batches = 0
         self.batch_sizes: List[int] = []
         self.overlapped_launches = 0   # batches launched while another was in flight
+        self.failed_batches = 0
         self.t0 = 0.0                  # engine-clock origin of arrival and finish times
 
     # ------------------------------------------------------------ accounting
@@ -155,8 +167,9 @@ class Engine:
         """Retire finished batches; returns the requests that finished."""
         finished: List[Request] = []
         still: List[_InFlight] = []
+        now = self.clock() - self.t0
         for f in self.inflight:
-            t = self.ex.finished_at(f.handle)
+            t = self.ex.finished_at(f.handle, now)
             if t is None:
                 still.append(f)
                 continue
@@ -200,9 +213,18 @@ class Engine:
                 r.admitted = now
                 r.batch_id = self.batches
             del self.queue[:len(take)]
+            try:
+                handle = self.ex.launch(take, slot, off, need_ws)
+            except Exception as e:                    # this batch fails alone
+                self.arena.release(off)
+                for r in take:
+                    r.failed = True
+                    r.error = f"{type(e).__name__}: {e}"
+                self.done.extend(take)
+                self.failed_batches += 1
+                continue
             if self.inflight:
                 self.overlapped_launches += 1
-            handle = self.ex.launch(take, slot, off, need_ws)
             self.inflight.append(_InFlight(self.batches, slot, take, handle, off, _align(need_ws), need_out))
             self.out_bytes += need_out
             self.peak_bytes = max(self.peak_bytes, self.bytes_in_use())
@@ -238,13 +260,15 @@ def run(engine: Engine, requests: Sequence[Request], sleep: Callable[[float], No
 
 
 def summarize(engine: Engine, requests: Sequence[Request], t0: float) -> dict:
-    ok = [r for r in requests if not r.rejected]
+    ok = [r for r in requests if not r.rejected and not r.failed]
     lat = np.array([r.latency for r in ok], dtype=np.float64) * 1e3 if ok else np.zeros(0)
     span = (max(r.finished for r in ok) - min(r.arrival for r in ok)) if ok else 0.0
     return {
         "requests": len(requests),
         "completed": len(ok),
-        "rejected": len(requests) - len(ok),
+        "rejected": sum(1 for r in requests if r.rejected),
+        "failed": sum(1 for r in requests if r.failed),
+        "failed_batches": engine.failed_batches,
         "batches": engine.batches,
         "mean_batch_frames": float(np.mean(engine.batch_sizes)) if engine.batch_sizes else 0.0,
         "overlapped_launches": engine.overlapped_launches,
@@ -294,9 +318,8 @@ class FakeExecutor:
         self.launches.append((slot, [r.rid for r in reqs], now))
         return {"end": now + self.cost([r.shape for r in reqs])}
 
-    def finished_at(self, h):
-        now = self.clock()
-        return h["end"] - self.t0 if now >= h["end"] else None
+    def finished_at(self, h, now):
+        return h["end"] - self.t0 if self.clock() >= h["end"] else None
 
     def release(self, h):
         pass
@@ -304,8 +327,11 @@ class FakeExecutor:
 
 class GpuExecutor:
     """Runs each admitted batch through p2s_batch_create/upload/launch on the
-    slot's stream, inside the engine's arena; finish times come from an event
-    recorded after the batch, measured from an event recorded at start."""
+    slot's stream, inside the engine's arena (one device buffer of the budget,
+    allocated once).  Every request brings its own output buffer (Request.out,
+    the shape of its image), so the executor allocates nothing per batch; a
+    batch is finished once the event recorded after its kernels has
+    completed, at the engine-clock time of the poll that sees it."""
 
     def __init__(self, sim, precision: str, arena_bytes: int, n_slots: int, options: Optional[dict] = None):
         import torch
@@ -315,15 +341,9 @@ class GpuExecutor:
         self.options = options or {}
         self.arena = torch.empty(_align(arena_bytes), dtype=torch.uint8, device="cuda")
         self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
-        self.t_ref = None
 
     def start(self, t0):
-        torch = self.torch
-        torch.cuda.synchronize()
-        self.t_ref = torch.cuda.Event(enable_timing=True)
-        self.t_ref.record()
-        torch.cuda.synchronize()
-        self.t0_host = t0
+        self.torch.cuda.synchronize()
 
     def shape_of(self, image):
         return tuple(int(v) for v in image.shape)
@@ -333,33 +353,32 @@ class GpuExecutor:
         return p2s.batch_workspace_bytes(list(shapes), self.sim.n_zernike, self.sim.basis.K, self.sim.corr_len_px)
 
     def out_bytes(self, shape):
-        c, h, w = shape
-        return _align(4 * c * h * w)
+        return 0                                      # outputs are the caller's
 
     def launch(self, reqs, slot, off, nbytes):
         from . import p2s
         torch = self.torch
+        for r in reqs:
+            if r.out is None or tuple(r.out.shape) != tuple(r.image.shape):
+                raise ValueError(f"request {r.rid}: needs an output buffer of its image's shape")
         s = self.streams[slot]
         ws = self.arena[off: off + _align(nbytes)]
-        with torch.cuda.stream(s):
-            outs = [torch.empty_like(r.image) for r in reqs]
-            b = p2s.Batch([r.image for r in reqs], outs, [r.d_over_r0 for r in reqs], [r.seed for r in reqs],
-                          self.sim.basis, self.sim.net, self.precision, ws, self.sim.n_zernike,
-                          self.sim.corr_len_px, self.sim.q_sampling, **self.options)
+        b = p2s.Batch([r.image for r in reqs], [r.out for r in reqs], [r.d_over_r0 for r in reqs],
+                      [r.seed for r in reqs], self.sim.basis, self.sim.net, self.precision, ws, self.sim.n_zernike,
+                      self.sim.corr_len_px, self.sim.q_sampling, **self.options)
+        try:
             b.upload(stream=s)
             b.launch(stream=s)
-            ev = torch.cuda.Event(enable_timing=True)
-            ev.record(s)
-        for r, o in zip(reqs, outs):
-            r.out = o
+        except Exception:
+            b.close()
+            raise
+        ev = torch.cuda.Event()
+        ev.record(s)
         return (b, ev)
 
-    def finished_at(self, h):
+    def finished_at(self, h, now):
         b, ev = h
-        if not ev.query():
-            return None
-        # device time since the reference event, which ran when the loop started
-        return self.t_ref.elapsed_time(ev) / 1e3
+        return now if ev.query() else None
 
     def release(self, h):
         b, ev = h

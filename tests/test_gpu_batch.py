@@ -207,3 +207,8 @@ def test_ragged_full_size_sampled(p2s, big_sim, prec):
     wl = S.workload("ragged")
     big = max(range(len(wl.frames)), key=lambda i: wl.frames[i].H * wl.frames[i].W * wl.frames[i].C)
     run_workload_sampled(p2s, big_sim, "ragged", prec, [0, 1, 199, big])
+
+
+def test_batch256_full_size_sampled_fp32(p2s, big_sim):
+    """The FP32 batched kernels at the full 64-frame RGB 256x256 size."""
+    run_workload_sampled(p2s, big_sim, "batch256", "fp32", [0, 31, 63])

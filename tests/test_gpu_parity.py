@@ -394,3 +394,45 @@ def test_errors_through_binding(p2s):
         with pytest.raises(p2s.P2SError) as e:
             p2s.blur(img, b5, torch.zeros((128 * 128, 16), device="cuda"), prec, torch.empty_like(img))
         assert e.value.code == p2s.P2S_EUNSUPPORTED
+
+
+def generic_xavier(dims, seed, bias_scale):
+    """Xavier-uniform weights and uniform biases as plain float32 draws (not
+    rounded to bfloat16-representable values), as a trained network would
+    have them."""
+    rng = np.random.default_rng(seed)
+    Ws, bs = [], []
+    for l in range(len(dims) - 1):
+        a = np.sqrt(6.0 / (dims[l] + dims[l + 1]))
+        Ws.append(rng.uniform(-a, a, size=(dims[l + 1], dims[l])).astype(np.float32))
+        bs.append(rng.uniform(-bias_scale, bias_scale, size=dims[l + 1]).astype(np.float32))
+    return Ws, bs
+
+
+def test_bf16_with_generic_fp32_weights(p2s):
+    """BF16 network and frame with weights that are not bf16-representable
+    (the BF16 path rounds them to bfloat16 once, at p2s_mlp_create), against
+    the oracle run with the original float32 weights.  Tolerances: network
+    output 5e-3 (weights rounded with unit roundoff 2^-9 = 2e-3 each; the
+    errors of a layer's 100 products average out to about 2^-9/sqrt(3) of the
+    output, and three layers add in quadrature: ~2e-3); end to end 1e-2 (the
+    weight error of w times the blur's median cancellation factor of ~7,
+    partly averaged over the frame)."""
+    wl = S.workload("single512")
+    fr = wl.frames[0]
+    Ws, bs = generic_xavier(wl.mlp_dims, 91, 0.05)
+    net = p2s.Mlp(Ws, bs)
+    H, W, nz = 128, 160, wl.n_zernike
+    Fh = synthetic_fields(nz, H, W, seed=5, scale=0.15)
+    w = torch.empty((H * W, wl.K), dtype=torch.float32, device="cuda")
+    p2s.mlp(net, dev(Fh), nz, H, W, "bf16", w)
+    ref = omlp.forward(Ws, bs, np.moveaxis(Fh[2:], 0, -1).reshape(H * W, nz - 2))
+    e_net = rel_l2(host(w), ref)
+    basis = oracle_basis("single512")
+    sim = p2s.Simulator(basis, Ws, bs, n_zernike=nz)
+    img = fr.image()
+    out = sim(dev(img), fr.d_over_r0, fr.field_seed, "bf16")
+    refo = osimulate(img, fr.d_over_r0, basis, Ws, bs, seed=fr.field_seed)["out"]
+    e_sim = rel_l2(host(out), refo)
+    print(f"generic float32 weights, BF16 path: network {e_net:.2e}, frame {e_sim:.2e}", flush=True)
+    assert e_net < 5e-3 and e_sim < 1e-2, (e_net, e_sim)

@@ -445,3 +445,20 @@ def test_fp8_blur_reduces_to_basis_blur_on_representable_operands():
     for k in range(K):
         step = 2.0 ** (5 - ex[k])           # 448 = 1.75 * 2^8: top binade spacing 2^5
         assert np.max(np.abs(qb[k] - b[k])) <= step / 2 + 1e-12
+
+
+def test_simulate_pixels_equals_whole_frame():
+    """The pointwise form used for large frames equals the whole-frame oracle
+    at every pixel (asymmetric random basis, biased network, RGB, ragged
+    size, strong tilt so that clamped samples occur)."""
+    from oracle.simulate import simulate_pixels
+    rng = np.random.default_rng(5)
+    C, H, W, K, P = 2, 23, 31, 6, 7
+    img = rng.uniform(0, 1, (C, H, W))
+    basis = rng.normal(size=(K, P, P))
+    Ws = [rng.normal(size=(9, 33)) * 0.3, rng.normal(size=(K, 9)) * 0.3]
+    bs = [rng.normal(size=9) * 0.1, rng.normal(size=K) * 0.1]
+    ref = simulate(img, 6.0, basis, Ws, bs, seed=3)["out"]
+    pix = [(c, y, x) for c in range(C) for y in range(H) for x in range(W)]
+    got = simulate_pixels(img, 6.0, basis, Ws, bs, 3, pix)
+    np.testing.assert_allclose(got, ref.reshape(-1), rtol=0, atol=1e-12 * np.abs(ref).max())

@@ -117,3 +117,64 @@ def test_poisson_arrivals():
     gaps = np.diff(a)
     assert abs(gaps.mean() - 1 / 500.0) < 0.03 / 500.0
     assert abs(gaps.std() / gaps.mean() - 1.0) < 0.03
+
+
+class FlakyExecutor(sv.FakeExecutor):
+    """Fake executor whose launches listed in `fail_on` raise `exc` (by launch
+    attempt number, from 0)."""
+
+    def __init__(self, *a, fail_on=(), exc=None, **k):
+        super().__init__(*a, **k)
+        self.attempts = 0
+        self.fail_on = set(fail_on)
+        self.exc = exc
+
+    def launch(self, reqs, slot, off, nbytes):
+        n = self.attempts
+        self.attempts += 1
+        if n in self.fail_on:
+            raise self.exc
+        return super().launch(reqs, slot, off, nbytes)
+
+
+def flaky(p2s, budget, exc, fail_on, max_frames=4):
+    clk = Clock()
+
+    def ws(shapes):
+        return p2s.batch_workspace_bytes(shapes, 35, 100)
+
+    def cost(shapes):
+        return sum(c * h * w for c, h, w in shapes) * 1e-9
+
+    ex = FlakyExecutor(clk, cost, ws, fail_on=fail_on, exc=exc)
+    eng = sv.Engine(ex, budget, n_slots=2, max_batch_frames=max_frames, clock=clk)
+    return eng, ex, clk
+
+
+@pytest.mark.parametrize("kind", ["enomem", "launch_error"])
+def test_failed_launch_fails_only_its_batch(p2s, kind):
+    exc = (p2s.P2SError(p2s.P2S_ENOMEM, "injected: device allocation failed") if kind == "enomem"
+           else RuntimeError("injected: kernel launch failed"))
+    budget = 4 * p2s.batch_workspace_bytes([(3, 256, 256)], 35, 100)
+    eng, ex, clk = flaky(p2s, budget, exc, fail_on={1}, max_frames=1)
+    reqs = [sv.Request(i, (3, 256, 256), 1.0, i, 0.0005 * i) for i in range(6)]
+    st = sv.run(eng, reqs, sleep=clk.sleep)
+    failed = [r for r in reqs if r.failed]
+    assert len(failed) == 1 and failed[0].rid == 1
+    assert "injected" in failed[0].error and failed[0].finished is None
+    assert st["failed"] == 1 and st["failed_batches"] == 1 and st["completed"] == 5
+    for r in reqs:
+        if not r.failed:
+            assert r.finished is not None and r.latency > 0
+    # the failed batch's arena block came back, and so did every other one
+    assert eng.arena.bytes_in_use == 0 and eng.arena.free_blocks == [(0, eng.arena.capacity)]
+    assert eng.idle() and st["peak_hbm_bytes"] <= budget
+
+
+def test_every_launch_failing_still_ends(p2s):
+    budget = 4 * p2s.batch_workspace_bytes([(1, 128, 128)], 35, 100)
+    eng, ex, clk = flaky(p2s, budget, RuntimeError("injected"), fail_on=set(range(100)))
+    reqs = [sv.Request(i, (1, 128, 128), 1.0, i, 0.0) for i in range(10)]
+    st = sv.run(eng, reqs, sleep=clk.sleep)
+    assert st["completed"] == 0 and st["failed"] == 10 and st["frames_per_s"] is None
+    assert eng.arena.bytes_in_use == 0 and eng.idle()
