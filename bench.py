@@ -163,7 +163,7 @@ def blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C):
                       "algorithmic_bytes_per_launch": 4 * (2 * C * H * W + H * W * K)}), flush=True)
 
 
-def batch_section(args, torch, p2s, S, pbasis):
+def batch_section(args, torch, p2s, S, pbasis, ptrain):
     """The two batch workloads (64 RGB 256x256 frames; 200 ragged frames) with
     the shared K=100, P=33 basis: BF16 and FP32 through the batched kernels
     (plan uploaded once, the launch captured in a HIP graph and replayed) and,
@@ -173,7 +173,7 @@ def batch_section(args, torch, p2s, S, pbasis):
     wl0 = S.workload("batch256")
     z, d = wl0.basis_draws()
     basis, _ = pbasis.learn_basis(z, d, wl0.K, wl0.P, wl0.n_zernike)
-    Ws, bs = wl0.mlp()
+    Ws, bs, _ = ptrain.load("p2s_shared", basis)          # trained for this basis
     sim = p2s.Simulator(basis, Ws, bs, n_zernike=wl0.n_zernike)
     out = {}
     samples = {}
@@ -265,7 +265,7 @@ def batch_section(args, torch, p2s, S, pbasis):
     return out, samples
 
 
-def serving_section(args, torch, p2s, S, pbasis):
+def serving_section(args, torch, p2s, S, pbasis, ptrain):
     """The serving workload: requests of 128..2048 RGB through the
     continuous-batching loop in BF16 under the HBM admission budget.  First
     all requests queued at once (the saturated request rate), then Poisson
@@ -279,7 +279,7 @@ def serving_section(args, torch, p2s, S, pbasis):
     wl = S.workload("serving")
     z, d = wl.basis_draws()
     basis, _ = pbasis.learn_basis(z, d, wl.K, wl.P, wl.n_zernike)
-    Ws, bs = wl.mlp()
+    Ws, bs, _ = ptrain.load("p2s_shared", basis)          # trained for this basis
     sim = p2s.Simulator(basis, Ws, bs, n_zernike=wl.n_zernike)
     frames = wl.frames[: args.serving_requests]
     t0 = time.perf_counter()
@@ -416,6 +416,7 @@ def main():
     import p2s_synth as S
     from paper_2107_11627_amd import basis as pbasis
     from paper_2107_11627_amd import p2s
+    from paper_2107_11627_amd import train as ptrain
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -430,7 +431,7 @@ def main():
     z, d = wl.basis_draws()
     basis, _ = pbasis.learn_basis(z, d, K, P, NZ)
     log(f"[bench] basis ready in {time.perf_counter() - t0:.1f} s")
-    Ws, bs = wl.mlp()
+    Ws, bs, net_meta = ptrain.load("p2s_single512", basis)   # the P2S network trained for this basis
     img_h = fr.image()
     sim = p2s.Simulator(basis, Ws, bs, n_zernike=NZ)
     img = torch.from_numpy(img_h).cuda()
@@ -554,8 +555,8 @@ def main():
                 "peak": PEAK_FP8_TFLOPS, "frac": (flops + nflops) / fp8_s / 1e12 / PEAK_FP8_TFLOPS,
                 "note": "the network's share runs on BF16 MFMA (peak 2500)"}
 
-    batches, batch_samples = (None, {}) if args.no_batches else batch_section(args, torch, p2s, S, pbasis)
-    serving, serving_samples = (None, None) if args.no_serving else serving_section(args, torch, p2s, S, pbasis)
+    batches, batch_samples = (None, {}) if args.no_batches else batch_section(args, torch, p2s, S, pbasis, ptrain)
+    serving, serving_samples = (None, None) if args.no_serving else serving_section(args, torch, p2s, S, pbasis, ptrain)
 
     cpu = None
     errs = None
@@ -621,7 +622,8 @@ def main():
         "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": "single512: 512x512 C=1 blob image, D/r0=3, 35 Zernike planes, K=100 basis of "
-                               "33x33, network 33-100-100-100, new field seed per frame",
+                               "33x33, network 33-100-100-100 (trained), new field seed per frame",
+                   "network": net_meta["file"],
                    "H": H, "W": W, "C": C, "K": K, "P": P, "n_zernike": NZ, "global_batch": 1},
         "latency_ms": {p: res[p]["latency_ms"] for p in res},
         "fp32": {"frames_per_s": res["fp32"]["frames_per_s"], "ms_per_frame": res["fp32"]["ms_per_frame"],

@@ -100,6 +100,7 @@ struct WFromMemory {
     int K, H, W;
     float* out;
     __device__ __forceinline__ void prefetch(int, int, int) {}
+    __device__ __forceinline__ void settle() {}
     __device__ __forceinline__ void begin(int, int, int, int) {}
     __device__ __forceinline__ void operator()(const floatx4 (&acc)[NBLK][NMB], int yw, int x0, int g, int m,
                                                int c) const {
@@ -133,6 +134,20 @@ struct WFromNetwork {
 #pragma unroll
         for (int b = 0; b < NBLK; ++b) pixc[b] = pixel(b, yw, x0, m, ok);
         mlp_load_inputs<NBLK>(*a, fields2, H * W, pixc, in);
+    }
+
+    // Take delivery of the field loads here, before the next window's copy is
+    // started: the compiler waits for every outstanding memory operation
+    // when a register loaded before a global_load_lds is first used, so a
+    // first use after the copy would wait for the copy as well.
+    __device__ __forceinline__ void settle() {
+        if constexpr (!EVAL) return;
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) asm volatile("" : "+v"(in[b][kc][e]));
     }
 
     // Before the convolutions, while no accumulator is live: the network for
@@ -247,7 +262,7 @@ __device__ __forceinline__ float* stage_lds() {
 }
 
 // The image window a tile item stages: rows y_lo.., columns x_lo.. of
-// channel plane ic (clamped to the image); ic == nullptr: no item.
+// channel plane ic (clamped to the image).
 struct Window {
     const float* ic;
     int H, W, y_lo, x_lo;
@@ -256,19 +271,30 @@ struct Window {
 // Start the copy of a window into the stage without registers: one
 // global_load_lds per row and wave (lane l copies column x_lo + l, clamped),
 // completed by s_waitcnt vmcnt(0) and a barrier before the stage is read.
+// Every wave issues the same compile-time number of copies (the last wave
+// repeats the last row: the same bytes to the same place), so the compiler
+// knows how many memory operations are younger than the loads issued before
+// the copy and waits for those alone, not for the copy.  w.ic must be valid.
 template <int SH>
 __device__ __forceinline__ void window_dma(float* stage, const Window& w) {
-    if (!w.ic) return;
+    constexpr int kWaves = kBlurThreads / 64;
+    constexpr int kRows = (SH + kWaves - 1) / kWaves;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int nw = (int)(blockDim.x >> 6);
     const int xx = min(max(w.x_lo + lane, 0), w.W - 1);
-    for (int r = wave; r < SH; r += nw) {
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+        const int r = min(wave + kWaves * i, SH - 1);
         const int yy = min(max(w.y_lo + r, 0), w.H - 1);
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(w.ic + (size_t)yy * w.W + xx),
                                          (__attribute__((address_space(3))) void*)(stage + r * kStagePitch), 4, 0, 0);
     }
 }
+
+// s_waitcnt immediate for vmcnt(0) alone (expcnt and lgkmcnt at their
+// maximum, no wait): vmcnt bits 3:0 and 15:14 zero, expcnt 6:4 = 7,
+// lgkmcnt 11:8 = 15.
+constexpr int kVmcnt0 = 0x0F70;
 
 __device__ __forceinline__ void wait_window() {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -408,7 +434,10 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
             colpk[r * CPITCH + q] = __builtin_bit_cast(uint4, to_bf16x8(v));
         });
         __syncthreads();
-        if constexpr (DMA) window_dma<SH>(stage, next);   // stage free until the next item
+        if constexpr (DMA) {
+            epi.settle();
+            window_dma<SH>(stage, next);          // stage free until the next item
+        }
         floatx4 acc[NBLK][NMB];
         // B-operand source of chunk 4 t + g for this lane's pixel block 0, and
         // the row step of that kind of chunk
@@ -448,6 +477,11 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
         };
         fetch(0, a0, p0);                         // in flight during the network
         epi.begin(y0 + lyw, x0, g, m);           // before the accumulators are live
+        // The window copy and the first operands have long landed; saying so
+        // (vmcnt(0) through the builtin, which the compiler's wait analysis
+        // sees) keeps it from treating the copy as pending inside the loop,
+        // where it would otherwise wait for every load at each step.
+        if constexpr (DMA) __builtin_amdgcn_s_waitcnt(kVmcnt0);
 #pragma unroll
         for (int b = 0; b < NBLK; ++b)
 #pragma unroll
@@ -532,7 +566,10 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
         colpk8[r * PITCH + q] = pack_e4m3x8(stage8 + r * SW + q + 2 * R, SW);
     });
     __syncthreads();
-    if constexpr (DMA) window_dma<SH>(stage8, next);   // stage free until the next item
+    if constexpr (DMA) {
+        epi.settle();
+        window_dma<SH>(stage8, next);             // stage free until the next item
+    }
     int sc[NMB];
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb) sc[mb] = scale[16 * mb + m];
@@ -587,6 +624,7 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
     };
     load_a(0, a0);                                // in flight during the network
     epi.begin(y0 + lyw, x0, g, m);               // before the accumulators are live
+    if constexpr (DMA) __builtin_amdgcn_s_waitcnt(kVmcnt0);   // as in the BF16 tile
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
 #pragma unroll
@@ -730,8 +768,10 @@ __global__ void __launch_bounds__(256) blur_mlp_kernel(const float* __restrict__
     if ((int)blockIdx.x < nt) window_dma<SH>(stage_lds<P, NBLK>(), tile_window<P, NBLK>(img, H, W, tiles_x, blockIdx.x));
     const float* lds_bias = stage_bf16_network(lds_w16, a, wg16, bias);   // the tile's first barrier publishes them
     for (int item = blockIdx.x; item < nt; item += gridDim.x) {
+        // the window copied after this item's last channel: the next item's,
+        // or (for the last item) this one's again, which nothing reads
         const int nx = item + (int)gridDim.x;
-        const Window after = nx < nt ? tile_window<P, NBLK>(img, H, W, tiles_x, nx) : Window{};
+        const Window after = tile_window<P, NBLK>(img, H, W, tiles_x, nx < nt ? nx : item);
         fused_item<P, NMB, NBLK, FP8>(img, C, H, W, bp, scale, a, lds_w16, lds_bias, fields2, out, tiles_x, item,
                                       after);
     }
@@ -759,7 +799,7 @@ __global__ void __launch_bounds__(256) blur_mlp_batch(const FrameDesc* __restric
         const int f = find_frame(first, n, item);
         const FrameDesc& d = fr[f];
         const int nx = item + (int)gridDim.x;
-        const Window after = nx < total ? batch_window<P, NMB, NBLK, FP8>(fr, first, n, nx) : Window{};
+        const Window after = batch_window<P, NMB, NBLK, FP8>(fr, first, n, nx < total ? nx : item);
         fused_item<P, NMB, NBLK, FP8>(d.image, d.C, d.H, d.W, bp, scale, a, lds_w16, lds_bias,
                                       d.fields + 2 * (size_t)d.H * d.W, d.blurred, d.tiles_x, item - first[f], after);
     }
@@ -908,12 +948,18 @@ hipError_t launch_blur_batch(const Basis& b, const BatchLaunch& bl, p2s_precisio
 
 namespace {
 
-// Pixel blocks per wave of the fused BF16 kernel: the blur accumulators
-// (4 NBLK NMB registers) and the network's live values must share the wave's
-// 256 accumulation-capable registers, so wide bases take 12-row or 8-row tiles.
+// Pixel blocks per wave of the fused kernels: the blur accumulators
+// (4 NBLK NMB registers), the network outputs they are dotted with (as many)
+// and the operands in flight share the wave's 512 registers, so wide bases
+// take 8-row or 4-row tiles.  Each basis operand a wave loads feeds NBLK
+// MFMAs, and these loads are what the convolution loop waits on (every wave
+// reads the basis from the L1 cache, whose bandwidth per CU is about what
+// 4 waves need at NBLK = 4), so FP8 keeps NBLK = 4 up to K = 112 as well
+// (at K = 112 a few network values spill to scratch, off the convolution
+// loop).
 constexpr int fused_nblk_bf16(int nmb) { return nmb >= 8 ? 2 : (nmb >= 4 ? 4 : 8); }
-constexpr int fused_nblk_fp8(int nmb) { return nmb >= 5 ? 2 : 4; }
-// FP8 instances whose registers fit without spilling (the others use the
+constexpr int fused_nblk_fp8(int nmb) { return nmb >= 8 ? 2 : 4; }
+// FP8 instances whose registers fit (the others use the
 // network kernel and the w-reading blur)
 constexpr bool fused_fp8_fits(int P, int nmb) { return nmb <= 7 && !(P == 17 && nmb >= 4); }
 

@@ -213,6 +213,61 @@ __device__ __forceinline__ void stockham(int N, int Ns, int lg_tpf, const float2
     }
 }
 
+// The same pass in place, for a transform that lives in one wave and whose
+// butterflies take at most MAXIT rounds of its threads: every thread reads
+// the inputs of all its butterflies before any thread writes, and a wave's
+// LDS operations complete in the order it issues them, so the pass may
+// overwrite its own input (one LDS buffer per transform instead of two).
+template <int R, int MAXIT, class Src, class Dst>
+__device__ __forceinline__ void stockham_inplace(int N, int Ns, int lg_tpf, const float2* __restrict__ tw, float sgn,
+                                                 Src&& src, Dst&& dst) {
+    const int nb = N / R;
+    const int f = threadIdx.x >> lg_tpf;
+    const int tpf = 1 << lg_tpf;
+    const int step = nb / Ns;
+    const float inv_ns = 1.0f / (float)Ns;
+    const int j0 = threadIdx.x & (tpf - 1);
+    float2 v[MAXIT][R];
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int j = j0 + it * tpf;
+        if (j < nb) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[it][r] = src(f, j + r * nb);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int j = j0 + it * tpf;
+        if (j >= nb) continue;
+        const int qj = __float2int_rd(((float)j + 0.5f) * inv_ns);
+        const int k = j - qj * Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            float2 w = tw[r * k * step];
+            w.y *= -sgn;
+            v[it][r] = cmul(v[it][r], w);
+        }
+        dft<R>(v[it], sgn);
+        const int base = qj * Ns * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) dst(f, base + q * Ns, v[it][q]);
+    }
+}
+
+template <class Src, class Dst>
+__device__ __forceinline__ void stockham_inplace_r(int R, int N, int Ns, int lg_tpf, const float2* tw, float sgn,
+                                                   Src&& src, Dst&& dst) {
+    switch (R) {
+        case 2: stockham_inplace<2, 2>(N, Ns, lg_tpf, tw, sgn, src, dst); break;
+        case 3: stockham_inplace<3, 2>(N, Ns, lg_tpf, tw, sgn, src, dst); break;
+        case 4: stockham_inplace<4, 2>(N, Ns, lg_tpf, tw, sgn, src, dst); break;
+        case 5: stockham_inplace<5, 2>(N, Ns, lg_tpf, tw, sgn, src, dst); break;
+        case 8: stockham_inplace<8, 2>(N, Ns, lg_tpf, tw, sgn, src, dst); break;
+        default: stockham_inplace<9, 2>(N, Ns, lg_tpf, tw, sgn, src, dst); break;
+    }
+}
+
 template <bool FIRST, class Src, class Dst>
 __device__ __forceinline__ void stockham_r(int R, int N, int Ns, int lg_tpf, const float2* tw, float sgn, Src&& src,
                                            Dst&& dst) {
@@ -272,15 +327,29 @@ __device__ __forceinline__ void pass_sync(int lg_tpf) {
     }
 }
 
+// Whether the middle passes of an N-point transform on 2^lg_tpf threads may
+// run in place: the transform lives in one wave (at most 64 threads) and no
+// middle pass needs more than two rounds of its threads.
+__host__ __device__ inline bool ifft_inplace_ok(int N, int lg_tpf, const int* rad, int nrad) {
+    if (lg_tpf > 6) return false;
+    for (int i = 1; i + 1 < nrad; ++i)
+        if (N / rad[i] > (2 << lg_tpf)) return false;
+    return true;
+}
+
 // Whole inverse transforms of one item: the first pass gathers its inputs
 // with src (band entries or zero), the middle passes run LDS to LDS at
 // stride ld, the last pass hands every output to out(f, index, value).
 // At least two passes (N >= 72 > the largest radix).  band_lo / band_hi:
 // the nonzero inputs lie in [0, band_lo] and [N - band_hi, N); when both
 // parts fit in one first-pass stride the sparse first pass is used.
+//
+// inplace: the middle passes overwrite their input (ifft_inplace_ok holds
+// for this transform), and b is not used.
 template <class Src, class Out>
 __device__ __forceinline__ void ifft_item(int N, int ld, int lg_tpf, const int* rad, int nrad, const float2* tw,
-                                          float2* a, float2* b, int band_lo, int band_hi, Src&& src, Out&& out) {
+                                          float2* a, float2* b, int band_lo, int band_hi, bool inplace, Src&& src,
+                                          Out&& out) {
     auto to_lds = [&](float2* buf) {
         return [buf, ld](int f, int i, float2 v) { buf[f * ld + i] = v; };
     };
@@ -295,11 +364,15 @@ __device__ __forceinline__ void ifft_item(int N, int ld, int lg_tpf, const int* 
     pass_sync(lg_tpf);
     int Ns = rad[0];
     for (int i = 1; i + 1 < nrad; ++i) {
-        stockham_r<false>(rad[i], N, Ns, lg_tpf, tw, 1.0f, from_lds(a), to_lds(b));
+        if (inplace) {
+            stockham_inplace_r(rad[i], N, Ns, lg_tpf, tw, 1.0f, from_lds(a), to_lds(a));
+        } else {
+            stockham_r<false>(rad[i], N, Ns, lg_tpf, tw, 1.0f, from_lds(a), to_lds(b));
+            float2* t = a;
+            a = b;
+            b = t;
+        }
         pass_sync(lg_tpf);
-        float2* t = a;
-        a = b;
-        b = t;
         Ns *= rad[i];
     }
     stockham_r<false>(rad[nrad - 1], N, Ns, lg_tpf, tw, 1.0f, from_lds(a), out);
@@ -344,9 +417,10 @@ __device__ __forceinline__ void fields_cols_item(const FieldPlan& fp, float2* __
                                  int lg_cpb, int q, int j0, float2* smem, bool fresh) {
     const int cpb = 1 << lg_cpb;
     const int N = fp.Nfy, ld = ld_of(N);
+    const bool inplace = ifft_inplace_ok(N, 8 - lg_cpb, fp.rad_y, fp.nrad_y);
     float2* buf0 = smem;
     float2* buf1 = smem + cpb * ld;
-    float2* tw = smem + 2 * cpb * ld;
+    float2* tw = smem + (inplace ? 1 : 2) * cpb * ld;
     float* filt = reinterpret_cast<float*>(tw + N);
     if (q == 0 && j0 == 0) fill_twiddles(twx_out, fp.Nfx);
     const int lg_tpf = 8 - lg_cpb;             // 256 threads
@@ -378,7 +452,7 @@ __device__ __forceinline__ void fields_cols_item(const FieldPlan& fp, float2* __
         const int j = j0 + c;
         if (y < H && j < Mx) Vq[(size_t)j * H + y] = v;
     };
-    ifft_item(N, ld, lg_tpf, fp.rad_y, fp.nrad_y, tw, buf0, buf1, fp.kcy, fp.kcy, noise, out);
+    ifft_item(N, ld, lg_tpf, fp.rad_y, fp.nrad_y, tw, buf0, buf1, fp.kcy, fp.kcy, inplace, noise, out);
     if (lg_tpf > 6) __syncthreads();           // LDS free for the next item (shared rows)
 }
 
@@ -389,9 +463,10 @@ __device__ __forceinline__ void fields_rows_item(const FieldPlan& fp, const floa
                                  const float2* __restrict__ twx, int lg_rpb, int q, int y0, float2* smem, bool fresh) {
     const int rpb = 1 << lg_rpb;
     const int N = fp.Nfx, ld = ld_of(N);
+    const bool inplace = ifft_inplace_ok(N, 8 - lg_rpb, fp.rad_x, fp.nrad_x);
     float2* buf0 = smem;
     float2* buf1 = smem + rpb * ld;
-    float2* tw = smem + 2 * rpb * ld;
+    float2* tw = smem + (inplace ? 1 : 2) * rpb * ld;
     const int H = fp.H, W = fp.W, Mx = fp.Mx, kcx = fp.kcx;
     if (fresh) {                               // first item of this frame in the workgroup
         __syncthreads();                       // every wave done with the previous frame's table
@@ -419,7 +494,7 @@ __device__ __forceinline__ void fields_rows_item(const FieldPlan& fp, const floa
         row0[x] = s0 * v.x;
         if (has1) row1[x] = s1 * v.y;
     };
-    ifft_item(N, ld, 8 - lg_rpb, fp.rad_x, fp.nrad_x, tw, buf0, buf1, kcx, Mx - 1 - kcx, band, out);
+    ifft_item(N, ld, 8 - lg_rpb, fp.rad_x, fp.nrad_x, tw, buf0, buf1, kcx, Mx - 1 - kcx, inplace, band, out);
     if (lg_rpb < 2) __syncthreads();           // LDS free for the next item (shared rows)
 }
 
@@ -510,8 +585,16 @@ __global__ void debug_noise_kernel(int Nfy, int Nfx, int pair, uint32_t k0, uint
 
 }  // namespace
 
-size_t fields_cols_lds(int N, int nb) { return (size_t)(2 * nb * (N | 1) + N) * 8 + (size_t)N * 4; }
-size_t fields_rows_lds(int N, int nb) { return (size_t)(2 * nb * (N | 1) + N) * 8; }
+// LDS buffers per transform: one when the middle passes run in place.
+static int lds_buffers(int N, int nb) {
+    int rad[12];
+    const int n = factor_radices(N, rad);
+    return n && ifft_inplace_ok(N, 8 - __builtin_ctz((unsigned)nb), rad, n) ? 1 : 2;
+}
+size_t fields_cols_lds(int N, int nb) {
+    return (size_t)(lds_buffers(N, nb) * nb * (N | 1) + N) * 8 + (size_t)N * 4;
+}
+size_t fields_rows_lds(int N, int nb) { return (size_t)(lds_buffers(N, nb) * nb * (N | 1) + N) * 8; }
 
 int fields_pick_lg(int N, size_t budget, bool cols) {
     int lg = 3;

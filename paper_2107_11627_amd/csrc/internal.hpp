@@ -129,7 +129,7 @@ __device__ __forceinline__ int find_frame(const int* __restrict__ first, int n, 
     return lo;
 }
 
-constexpr size_t kColsLdsBudget = 96 * 1024;
+constexpr size_t kColsLdsBudget = 48 * 1024;
 constexpr size_t kRowsLdsBudget = 48 * 1024;
 size_t fields_cols_lds(int N, int nb);
 size_t fields_rows_lds(int N, int nb);

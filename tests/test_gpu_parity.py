@@ -436,3 +436,23 @@ def test_bf16_with_generic_fp32_weights(p2s):
     e_sim = rel_l2(host(out), refo)
     print(f"generic float32 weights, BF16 path: network {e_net:.2e}, frame {e_sim:.2e}", flush=True)
     assert e_net < 5e-3 and e_sim < 1e-2, (e_net, e_sim)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 3e-3), ("fp8", 3e-3)])
+def test_simulate_trained_network(p2s, prec, tol):
+    """A whole 512x512 frame with the trained P2S network of that workload's
+    basis (weights are data: the kernels are the same) against the oracle;
+    FP8 against the oracle fed the same E4M3-rounded blur operands."""
+    from paper_2107_11627_amd import train
+    wl = S.workload("single512")
+    fr = wl.frames[0]
+    basis = oracle_basis("single512")
+    Ws, bs, _ = train.load("p2s_single512", basis)
+    sim = p2s.Simulator(basis, Ws, bs, n_zernike=wl.n_zernike)
+    img = fr.image()
+    out = sim(dev(img), fr.d_over_r0, fr.field_seed, prec)
+    ref = osimulate(img, fr.d_over_r0, basis, Ws, bs, seed=fr.field_seed,
+                    blur_operands="fp8" if prec == "fp8" else "exact")["out"]
+    err = rel_l2(host(out), ref)
+    print(f"trained network, {prec}: rel-L2 vs oracle {err:.2e}", flush=True)
+    assert err < tol
