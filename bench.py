@@ -138,6 +138,108 @@ def mlp_blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C, dims):
                       "algorithmic_bytes_per_launch": 4 * (2 * C * H * W + (NZ - 2) * H * W)}), flush=True)
 
 
+def pipeline_times(torch, p2s, sim, img, fr, NZ, H, W, prec, frames, stream, seed0=5000):
+    """The network-and-blur kernel's average duration under the same
+    sustained load as the frame benchmark (a kernel run alone back to back,
+    or right after lighter work, runs at other clocks): the frame as its
+    three stage calls (fields, network and blur in one kernel, warp), with no
+    synchronisation, `frames` frames
+      (a) with HIP events on the launch stream around every network-and-blur
+          launch (each event adds a little time of its own), and
+      (b) back to back with and without that kernel, events only around the
+          whole loop: the difference per frame is the kernel's share.
+    Returns (events mean us, difference us, frame us)."""
+    F = torch.empty((NZ, H, W), dtype=torch.float32, device="cuda")
+    fws = torch.empty(p2s.fields_workspace_bytes(H, W, NZ), dtype=torch.uint8, device="cuda")
+    bl = torch.empty_like(img)
+    out = torch.empty_like(img)
+
+    def loop(with_kernel, ev=None):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(frames):
+            p2s.make_fields(H, W, fr.d_over_r0, NZ, seed0 + 10 + i, F, fws)
+            if ev is not None:
+                ev[i][0].record(stream)
+            if with_kernel:
+                p2s.mlp_blur(sim.net, F, NZ, img, sim.basis, prec, bl)
+            if ev is not None:
+                ev[i][1].record(stream)
+            p2s.warp(bl, F, out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / frames
+
+    for i in range(3):
+        p2s.make_fields(H, W, fr.d_over_r0, NZ, seed0 + i, F, fws)
+        p2s.mlp_blur(sim.net, F, NZ, img, sim.basis, prec, bl)
+        p2s.warp(bl, F, out)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(frames)]
+    loop(True, ev)
+    per = float(np.mean([a.elapsed_time(b) * 1e3 for a, b in ev]))
+    full = loop(True)
+    without = loop(False)
+    full = min(full, loop(True))
+    return per, full - without, full
+
+
+def pipeline_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C, dims):
+    """The dominant kernel timed inside the frame pipeline (pipeline_times),
+    args.steps frames: the command whose kernel trace is committed beside the
+    benchmark's roofline figure."""
+    ev_us, us, frame_us = pipeline_times(torch, p2s, sim, img, fr, NZ, H, W, args.precision, args.steps,
+                                         torch.cuda.current_stream())
+    fl = blur_flops(C, H, W, K, P) + mlp_flops(H, W, dims)
+    print(json.dumps({"mode": "pipeline", "precision": args.precision, "frames": args.steps,
+                      "mlp_blur_avg_us": us, "mlp_blur_events_us": ev_us, "frame_us": frame_us,
+                      "TFLOPs": fl / us / 1e6, "algorithmic_flops_per_launch": fl}), flush=True)
+
+
+def mlp_mode(args, torch, p2s, sim, fr, NZ, H, W, K, dims):
+    """Only the P2S network kernel (w written to memory), args.steps launches
+    (for counter runs)."""
+    F = torch.empty((NZ, H, W), dtype=torch.float32, device="cuda")
+    fws = torch.empty(p2s.fields_workspace_bytes(H, W, NZ), dtype=torch.uint8, device="cuda")
+    wbuf = torch.empty((H * W, K), dtype=torch.float32, device="cuda")
+    p2s.make_fields(H, W, fr.d_over_r0, NZ, fr.field_seed, F, fws)
+    for _ in range(args.warmup):
+        p2s.mlp(sim.net, F, NZ, H, W, args.precision, wbuf)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        p2s.mlp(sim.net, F, NZ, H, W, args.precision, wbuf)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / args.steps
+    fl = mlp_flops(H, W, dims)
+    print(json.dumps({"mode": "mlp", "precision": args.precision, "avg_us": us, "TFLOPs": fl / us / 1e6,
+                      "algorithmic_flops_per_launch": fl}), flush=True)
+
+
+def warp_mode(args, torch, p2s, sim, img, fr, NZ, H, W):
+    """Only the tilt warp of the workload, args.steps launches (for counter
+    runs)."""
+    F = torch.empty((NZ, H, W), dtype=torch.float32, device="cuda")
+    fws = torch.empty(p2s.fields_workspace_bytes(H, W, NZ), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(img)
+    p2s.make_fields(H, W, fr.d_over_r0, NZ, fr.field_seed, F, fws)
+    for _ in range(args.warmup):
+        p2s.warp(img, F, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        p2s.warp(img, F, out)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / args.steps
+    nbytes = 4 * (2 * img.numel() + 2 * H * W)
+    print(json.dumps({"mode": "warp", "avg_us": us, "algorithmic_bytes_per_launch": nbytes,
+                      "GBps": nbytes / us / 1e3}), flush=True)
+
+
 def blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C):
     """Only the fused blur of the workload, args.steps launches, on weights
     from one network evaluation."""
@@ -393,6 +495,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--latency-frames", type=int, default=200)
     ap.add_argument("--stage-reps", type=int, default=20)
+    ap.add_argument("--pipeline-frames", type=int, default=200)
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -401,11 +504,14 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-slots", type=int, default=2)
     ap.add_argument("--serving-max-batch", type=int, default=16)
-    ap.add_argument("--mode", choices=["frame", "blur", "mlp_blur", "fields", "copy"], default="frame",
-                    help="frame: the benchmark; blur / mlp_blur: only the blur kernel, or the network-and-blur "
-                         "kernel, of the workload (for counter runs); "
+    ap.add_argument("--mode", choices=["frame", "blur", "mlp", "mlp_blur", "pipeline", "fields", "warp", "copy"],
+                    default="frame",
+                    help="frame: the benchmark; blur / mlp / mlp_blur / fields / warp: only that kernel of the "
+                         "workload (for counter runs); pipeline: the network-and-blur kernel timed inside "
+                         "back-to-back frames (the benchmark's roofline timing); "
                          "copy: a plain device copy of known size (calibrates byte counters)")
-    ap.add_argument("--precision", choices=["bf16", "fp32", "fp8"], default="bf16", help="precision of --mode blur")
+    ap.add_argument("--precision", choices=["bf16", "fp32", "fp8"], default="bf16",
+                    help="precision of the single-kernel modes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (frames are independent and "
@@ -448,6 +554,12 @@ def main():
         return fields_mode(args, torch, p2s, fr, NZ, H, W)
     if args.mode == "mlp_blur":
         return mlp_blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C, wl.mlp_dims)
+    if args.mode == "pipeline":
+        return pipeline_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C, wl.mlp_dims)
+    if args.mode == "warp":
+        return warp_mode(args, torch, p2s, sim, img, fr, NZ, H, W)
+    if args.mode == "mlp":
+        return mlp_mode(args, torch, p2s, sim, fr, NZ, H, W, K, wl.mlp_dims)
 
     res = {}
     outs = {}
@@ -512,18 +624,14 @@ def main():
             del stages["mlp_blur"]
         res[prec]["stages_us"] = {k: float(np.mean(v)) for k, v in stages.items()}
         if fused:
-            # the dominant kernel's average duration over back-to-back launches
-            # (one launch after lighter kernels runs faster than in steady state)
-            for _ in range(2):
-                p2s.mlp_blur(sim.net, F, NZ, img, sim.basis, prec, bl)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(args.stage_reps):
-                p2s.mlp_blur(sim.net, F, NZ, img, sim.basis, prec, bl)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            res[prec]["mlp_blur_loop_us"] = e0.elapsed_time(e1) * 1e3 / args.stage_reps
-            log(f"[bench] {prec} network+blur kernel back to back: {res[prec]['mlp_blur_loop_us']:.1f} us")
+            # the dominant kernel's average duration inside the frame pipeline
+            ev_us, us, frame_us = pipeline_times(torch, p2s, sim, img, fr, NZ, H, W, prec, args.pipeline_frames,
+                                                 stream)
+            res[prec]["mlp_blur_loop_us"] = us
+            res[prec]["mlp_blur_events_us"] = ev_us
+            res[prec]["pipeline_frame_us"] = frame_us
+            log(f"[bench] {prec} network+blur kernel inside the frame pipeline: {us:.1f} us "
+                f"(events around each launch: {ev_us:.1f} us; {frame_us:.1f} us per frame)")
         log(f"[bench] {prec} stages (us): " + ", ".join(f"{k} {v:.1f}" for k, v in res[prec]["stages_us"].items()))
         del wbuf, fws, bl
 
@@ -544,13 +652,16 @@ def main():
                 "algorithmic_flops_per_launch": flops + nflops,
                 "algorithmic_flops_split": {"blur": flops, "network": nflops},
                 "avg_launch_us": fused_s * 1e6, "src_digest": src_digest(*kernel_src),
+                "timing": f"{args.pipeline_frames} back-to-back frames (fields, network and blur, warp) with and "
+                          f"without the kernel, per-frame difference, as bench.py --mode pipeline",
+                "events_around_each_launch_us": res["bf16"]["mlp_blur_events_us"],
                 "blur_only": {"kernel": "blur_bf16_kernel<33,7,8> (w read from memory)", "avg_launch_us": blur_s * 1e6,
                               "achieved": flops / blur_s / 1e12, "frac": flops / blur_s / 1e12 / PEAK_BF16_TFLOPS}}
     fp32_blur_s = res["fp32"]["stages_us"]["blur"] * 1e-6
     fp32_roof = {"bound": "mfma", "achieved": flops / fp32_blur_s / 1e12, "peak": PEAK_FP32_TFLOPS,
                  "frac": flops / fp32_blur_s / 1e12 / PEAK_FP32_TFLOPS}
-    fp8_s = res["fp8"]["stages_us"]["mlp_blur"] * 1e-6
-    fp8_roof = {"bound": "mfma", "kernel": "blur_mlp_kernel<33,7,2,fp8> (FP8 blur, BF16 network)",
+    fp8_s = res["fp8"]["mlp_blur_loop_us"] * 1e-6
+    fp8_roof = {"bound": "mfma", "kernel": "blur_mlp_kernel<33,7,4,fp8> (FP8 blur, BF16 network)",
                 "achieved": (flops + nflops) / fp8_s / 1e12,
                 "peak": PEAK_FP8_TFLOPS, "frac": (flops + nflops) / fp8_s / 1e12 / PEAK_FP8_TFLOPS,
                 "note": "the network's share runs on BF16 MFMA (peak 2500)"}

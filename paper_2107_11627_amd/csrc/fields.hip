@@ -176,10 +176,27 @@ __device__ __forceinline__ void dft(float2 (&v)[R], float sgn) {
     }
 }
 
+// w^r for r = 1 .. R-1 from w (|w| = 1), by products in a shallow tree
+// (w^2 = w w, w^3 = w^2 w, w^4 = w^2 w^2, ...): at most three roundings deep,
+// so each power is within a few ulp of the exact root, and one table read
+// replaces R - 1.
+template <int R>
+__device__ __forceinline__ void twiddle_powers(float2 w, float2 (&p)[R]) {
+    p[1] = w;
+    if constexpr (R > 2) p[2] = cmul(w, w);
+    if constexpr (R > 3) p[3] = cmul(p[2], w);
+    if constexpr (R > 4) p[4] = cmul(p[2], p[2]);
+    if constexpr (R > 5) p[5] = cmul(p[4], w);
+    if constexpr (R > 6) p[6] = cmul(p[4], p[2]);
+    if constexpr (R > 7) p[7] = cmul(p[4], p[3]);
+    if constexpr (R > 8) p[8] = cmul(p[4], p[4]);
+}
+
 // One Stockham pass of radix R over the transforms of one work item, each of
 // length N with tpf = 2^lg_tpf threads; Ns = product of the radices already
 // applied.  Butterfly j reads x[j + r N/R] (src(f, index)), multiplies by
-// the twiddles W_N^(r k N/(Ns R)) (k = j mod Ns; none in the first pass, where
+// the twiddles W_N^(r k N/(Ns R)) (k = j mod Ns; the table gives r = 1, the
+// other powers follow by products; none in the first pass, where
 // Ns = 1) and writes X[(j / Ns) Ns R + k + q Ns] (dst(f, index, value)).
 // j / Ns is formed as floor((j + 0.5) / Ns) in FP32, exact for these sizes.
 // tw[q] = exp(-2 pi i q / N); the inverse (sgn = +1) conjugates it.
@@ -199,12 +216,12 @@ __device__ __forceinline__ void stockham(int N, int Ns, int lg_tpf, const float2
         if constexpr (!FIRST) {
             const int qj = __float2int_rd(((float)j + 0.5f) * inv_ns);
             const int k = j - qj * Ns;
+            float2 w = tw[k * step];
+            w.y *= -sgn;
+            float2 wp[R];
+            twiddle_powers<R>(w, wp);
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                float2 w = tw[r * k * step];
-                w.y *= -sgn;
-                v[r] = cmul(v[r], w);
-            }
+            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], wp[r]);
             base = qj * Ns * R + k;
         }
         dft<R>(v, sgn);
@@ -242,12 +259,12 @@ __device__ __forceinline__ void stockham_inplace(int N, int Ns, int lg_tpf, cons
         if (j >= nb) continue;
         const int qj = __float2int_rd(((float)j + 0.5f) * inv_ns);
         const int k = j - qj * Ns;
+        float2 w = tw[k * step];
+        w.y *= -sgn;
+        float2 wp[R];
+        twiddle_powers<R>(w, wp);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-            float2 w = tw[r * k * step];
-            w.y *= -sgn;
-            v[it][r] = cmul(v[it][r], w);
-        }
+        for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], wp[r]);
         dft<R>(v[it], sgn);
         const int base = qj * Ns * R + k;
 #pragma unroll
