@@ -62,7 +62,9 @@ typedef enum {
                          clamping to +-448; basis function k scaled by a power
                          of two 2^e_k, max |phi_k| 2^e_k <= 448, before
                          rounding, the scale undone inside the MFMA), FP32
-                         accumulation; the network runs as in P2S_BF16       */
+                         accumulation; the network on BF16 MFMA with its
+                         activations as bf16 alone (no lo part: the FP8
+                         blur's error is far larger than what it removes)    */
 } p2s_precision;
 
 /* Opaque, immutable, device-resident handles; safe to share across streams. */
@@ -153,8 +155,9 @@ int p2s_make_fields(int H, int W, double D_over_r0, int n_zernike, uint64_t seed
 /* Stage 2: the P2S network at every pixel (Sec. 3.3).  Reads planes
  * 2 .. n_zernike-1 of `fields` (device [n_zernike][H][W]); requires
  * n_zernike - 2 == the network's input width.  Writes w: device float32
- * [H*W][K], K = the network's output width.  precision: P2S_FP32, or
- * P2S_BF16 / P2S_FP8E4M3 (both run the network in BF16). */
+ * [H*W][K], K = the network's output width.  precision: P2S_FP32, P2S_BF16
+ * (BF16 MFMA, activations as bf16 hi + lo) or P2S_FP8E4M3 (BF16 MFMA,
+ * activations as bf16 alone). */
 int p2s_mlp(p2s_mlp_t mlp, const float* fields, int n_zernike, int H, int W,
             p2s_precision precision, float* w, void* stream);
 

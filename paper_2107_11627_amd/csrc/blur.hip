@@ -108,7 +108,7 @@ struct WFromMemory {
     }
 };
 
-template <int NMB, int NBLK, bool EVAL>
+template <int NMB, int NBLK, bool EVAL, bool LO = true>
 struct WFromNetwork {
     const MlpArgs* a;
     const uint4* lds_w16;
@@ -161,7 +161,7 @@ struct WFromNetwork {
         for (int b0 = 0; b0 < NBLK; b0 += GB) {
             const float (&ig)[GB][2][8] = *reinterpret_cast<const float (*)[GB][2][8]>(&in[b0]);
             float (&og)[GB][NMB][4] = *reinterpret_cast<float (*)[GB][NMB][4]>(&wv[b0]);
-            mlp_bf16_eval<NMB, GB>(*a, lds_w16, bias, ig, og);
+            mlp_bf16_eval<NMB, GB, LO>(*a, lds_w16, bias, ig, og);
         }
     }
 
@@ -734,13 +734,15 @@ __device__ __forceinline__ void fused_item(const float* img, int C, int H, int W
     // channel 0 runs the network; the other channels reuse its weights (a
     // separate instance of the tile code, so that the network's registers
     // are not held across the channel loop)
-    WFromNetwork<NMB, NBLK, true> first{&a, lds_w16, bias, fields2, H, W, out, {}, {}};
+    // the FP8 blur's network takes bf16 activations alone (as p2s_mlp does
+    // for that precision), the BF16 blur's a bf16 hi + lo pair
+    WFromNetwork<NMB, NBLK, true, !FP8> first{&a, lds_w16, bias, fields2, H, W, out, {}, {}};
     if constexpr (FP8)
         blur_fp8_tile<P, NMB, NBLK, true>(img, H, W, bp, scale, tiles_x, tile, 0, first, next_of(0));
     else
         blur_bf16_tile<P, NMB, NBLK, true>(img, H, W, bp, tiles_x, tile, 0, first, next_of(0));
     if (C == 1) return;
-    WFromNetwork<NMB, NBLK, false> rest{&a, lds_w16, bias, fields2, H, W, out, {}, {}};
+    WFromNetwork<NMB, NBLK, false, !FP8> rest{&a, lds_w16, bias, fields2, H, W, out, {}, {}};
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
 #pragma unroll

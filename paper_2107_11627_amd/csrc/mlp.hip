@@ -193,7 +193,7 @@ __device__ __forceinline__ void store_w16(const float (&act)[kNb16][MB][4], floa
 
 // The wave's blocks two at a time: two blocks need about half the registers
 // of a SIMD (two activation sets), four would need all of them.
-template <int MB>
+template <int MB, bool LO>
 __device__ __forceinline__ void eval_halves(const MlpArgs& a, const uint4* __restrict__ lds_w16,
                                             const float* __restrict__ bias, const float (&in)[kNb16][2][8],
                                             float (&out)[kNb16][MB][4]) {
@@ -201,7 +201,7 @@ __device__ __forceinline__ void eval_halves(const MlpArgs& a, const uint4* __res
     for (int b0 = 0; b0 < kNb16; b0 += 2) {
         const float (&ig)[2][2][8] = *reinterpret_cast<const float (*)[2][2][8]>(&in[b0]);
         float (&og)[2][MB][4] = *reinterpret_cast<float (*)[2][MB][4]>(&out[b0]);
-        mlp_bf16_eval<MB, 2>(a, lds_w16, bias, ig, og);
+        mlp_bf16_eval<MB, 2, LO>(a, lds_w16, bias, ig, og);
     }
 }
 
@@ -212,7 +212,9 @@ __device__ __forceinline__ void bf16_group_pixels(int grp, int HW, int (&pixc)[k
     for (int nb = 0; nb < kNb16; ++nb) pixc[nb] = min(pix0 + nb * 16 + (lane & 15), HW - 1);
 }
 
-template <int MB>
+// LO: activations as bf16 hi + lo (P2S_BF16); without: bf16 alone (the
+// network of P2S_FP8E4M3).
+template <int MB, bool LO>
 __global__ void __launch_bounds__(kWaves16 * 64) mlp_bf16_kernel(MlpArgs a, const float* __restrict__ fields,
                                                                  const uint4* __restrict__ wg,
                                                                  const float* __restrict__ bias,
@@ -242,12 +244,12 @@ __global__ void __launch_bounds__(kWaves16 * 64) mlp_bf16_kernel(MlpArgs a, cons
             mlp_load_inputs<kNb16>(a, fields, a.HW, pixc, in);
         }
         float outv[kNb16][MB][4];
-        eval_halves<MB>(a, lds_w16, lds_bias, cur, outv);
+        eval_halves<MB, LO>(a, lds_w16, lds_bias, cur, outv);
         store_w16<MB>(outv, wout, cur0, lane & 15, lane >> 4, a.HW, a.K);
     }
 }
 
-template <int MB>
+template <int MB, bool LO>
 __global__ void __launch_bounds__(kWaves16 * 64) mlp_bf16_batch(MlpArgs a, const FrameDesc* __restrict__ fr,
                                                                 const int* __restrict__ first, int n,
                                                                 const uint4* __restrict__ wg,
@@ -264,7 +266,7 @@ __global__ void __launch_bounds__(kWaves16 * 64) mlp_bf16_batch(MlpArgs a, const
         bf16_group_pixels(item - first[f], HW, pixc, pix0);
         float in[kNb16][2][8], outv[kNb16][MB][4];
         mlp_load_inputs<kNb16>(a, fr[f].fields + 2 * (size_t)HW, HW, pixc, in);
-        eval_halves<MB>(a, lds_w16, lds_bias, in, outv);
+        eval_halves<MB, LO>(a, lds_w16, lds_bias, in, outv);
         store_w16<MB>(outv, fr[f].w, pix0, lane & 15, lane >> 4, HW, a.K);
     }
 }
@@ -274,8 +276,9 @@ template <int MB>
 hipError_t set_attrs() {
     static bool attr = false;
     if (!attr) {
-        const void* ks[] = {(const void*)mlp_f32_kernel<MB>, (const void*)mlp_bf16_kernel<MB>,
-                            (const void*)mlp_f32_batch<MB>, (const void*)mlp_bf16_batch<MB>};
+        const void* ks[] = {(const void*)mlp_f32_kernel<MB>,        (const void*)mlp_bf16_kernel<MB, true>,
+                            (const void*)mlp_bf16_kernel<MB, false>, (const void*)mlp_f32_batch<MB>,
+                            (const void*)mlp_bf16_batch<MB, true>,   (const void*)mlp_bf16_batch<MB, false>};
         for (const void* k : ks) {
             hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             if (e != hipSuccess) return e;
@@ -313,8 +316,12 @@ hipError_t launch_mb_batch(const Mlp& mm, const MlpArgs& a0, const BatchLaunch& 
     if (prec == P2S_FP32)
         hipLaunchKernelGGL(mlp_f32_batch<MB>, dim3(bl.grid[ST_MLP]), dim3(kWaves * 64), mm.bytes32, s, a, bl.frames,
                            first, bl.n, mm.w32, mm.bias);
+    else if (prec == P2S_BF16)
+        hipLaunchKernelGGL((mlp_bf16_batch<MB, true>), dim3(bl.grid[ST_MLP]), dim3(kWaves16 * 64),
+                           mm.bytes16 + 4 * (size_t)a.nbias, s, a, bl.frames,
+                           first, bl.n, reinterpret_cast<const uint4*>(mm.w16), mm.bias);
     else
-        hipLaunchKernelGGL(mlp_bf16_batch<MB>, dim3(bl.grid[ST_MLP]), dim3(kWaves16 * 64),
+        hipLaunchKernelGGL((mlp_bf16_batch<MB, false>), dim3(bl.grid[ST_MLP]), dim3(kWaves16 * 64),
                            mm.bytes16 + 4 * (size_t)a.nbias, s, a, bl.frames,
                            first, bl.n, reinterpret_cast<const uint4*>(mm.w16), mm.bias);
     return hipGetLastError();
@@ -335,8 +342,14 @@ hipError_t launch_mb(const Mlp& mm, const MlpArgs& a0, const float* fields, p2s_
                            mm.bias, w);
     } else {
         fill_weight_args(mm, prec, a);
-        hipLaunchKernelGGL(mlp_bf16_kernel<MB>, dim3(grid), dim3(kWaves16 * 64), mm.bytes16 + 4 * (size_t)a.nbias, s,
-                           a, fields, reinterpret_cast<const uint4*>(mm.w16), mm.bias, w);
+        if (prec == P2S_BF16)
+            hipLaunchKernelGGL((mlp_bf16_kernel<MB, true>), dim3(grid), dim3(kWaves16 * 64),
+                               mm.bytes16 + 4 * (size_t)a.nbias, s, a, fields, reinterpret_cast<const uint4*>(mm.w16),
+                               mm.bias, w);
+        else
+            hipLaunchKernelGGL((mlp_bf16_kernel<MB, false>), dim3(grid), dim3(kWaves16 * 64),
+                               mm.bytes16 + 4 * (size_t)a.nbias, s, a, fields, reinterpret_cast<const uint4*>(mm.w16),
+                               mm.bias, w);
     }
     return hipGetLastError();
 }

@@ -106,7 +106,10 @@ __device__ __forceinline__ void load_pair(PairW<NKC>& d, const uint4* __restrict
 // The values are overwritten and lo holds a temporary between the slices,
 // so the split needs no registers beyond its source and destination.
 // Dwords d with 2 d >= zero_from hold a padding block: constant zero.
-template <int NB, int NC, bool RELU>
+//
+// LO = false: the activations enter as bf16 alone (no lo part): only the
+// first slice of each dword does work.
+template <int NB, int NC, bool RELU, bool LO = true>
 __device__ __forceinline__ void split_slice(int s, floatx4 (&v)[2][NB], int zero_from, u32x4 (&hi)[NB][NC],
                                             u32x4 (&lo)[NB][NC], int col) {
     const int nb = s >> 3, d = (s >> 1) & 3;
@@ -114,7 +117,7 @@ __device__ __forceinline__ void split_slice(int s, floatx4 (&v)[2][NB], int zero
     if (2 * d >= zero_from) {
         if ((s & 1) == 0) {
             hi[nb][col][d] = 0u;
-            lo[nb][col][d] = 0u;
+            if constexpr (LO) lo[nb][col][d] = 0u;
         }
         return;
     }
@@ -124,8 +127,8 @@ __device__ __forceinline__ void split_slice(int s, floatx4 (&v)[2][NB], int zero
             v[j][nb][i + 1] = relu(v[j][nb][i + 1]);
         }
         hi[nb][col][d] = pk_bf16(v[j][nb][i], v[j][nb][i + 1]);
-        lo[nb][col][d] = hi[nb][col][d] << 16;
-    } else {
+        if constexpr (LO) lo[nb][col][d] = hi[nb][col][d] << 16;
+    } else if constexpr (LO) {
         // (the elements are copied out first: __builtin_bit_cast applied to
         // a vector element lvalue reads element 0)
         const uint32_t t0 = lo[nb][col][d], t1 = hi[nb][col][d] & 0xFFFF0000u;
@@ -143,23 +146,27 @@ __device__ __forceinline__ void split_slice(int s, floatx4 (&v)[2][NB], int zero
 // barrier after each MFMA keeps the interleave as written (the hardware
 // issues in order, so VALU placed after a run of MFMAs would leave the matrix
 // pipe idle while it issues).
-template <int NB, int NKC, int JP, class Slot>
+//
+// LO = false: the bf16 activations alone, one MFMA per (chunk, block, pixel
+// block), and the caller's slot after every MFMA (the same slot numbering).
+template <int NB, int NKC, int JP, bool LO, class Slot>
 __device__ __forceinline__ void pair_mfma(const PairW<NKC>& w, const u32x4 (&xh)[NB][NKC], const u32x4 (&xl)[NB][NKC],
                                           floatx4 (&c)[2][NB], Slot&& slot) {
+    constexpr int NH = LO ? 2 : 1;
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < NH; ++h)
 #pragma unroll
             for (int j = 0; j < JP; ++j)
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const int t = ((kc * 2 + h) * JP + j) * NB + nb;
+                    const int t = ((kc * NH + h) * JP + j) * NB + nb;
                     const bf16x8 x = __builtin_bit_cast(bf16x8, h ? xl[nb][kc] : xh[nb][kc]);
                     c[j][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.w[j][kc], x, (kc == 0 && h == 0) ? w.b[j]
                                                                                                           : c[j][nb],
                                                                         0, 0, 0);
-                    if (t & 1) slot(t >> 1, kc);
+                    if (LO ? (t & 1) != 0 : true) slot(LO ? t >> 1 : t, kc);
                     __builtin_amdgcn_sched_barrier(0);
                 }
 }
@@ -181,7 +188,7 @@ __device__ __forceinline__ void slices_of_slot(int k, int nslots, int& s0, int& 
 // The ReLU + split of pair p - 1 runs between the MFMAs of pair p; the last
 // pair's accumulators leave in pout for the next layer.  LAST: the pairs go
 // to out, no activation.
-template <int MB, int NB, int NKC, int NKCN, bool PEND, bool LAST>
+template <int MB, int NB, int NKC, int NKCN, bool PEND, bool LAST, bool LO>
 __device__ __forceinline__ void layer_bf16(const uint4* __restrict__ wl, const float* __restrict__ lb,
                                            const PairW<NKC>& w0, const uint4* __restrict__ wln,
                                            const float* __restrict__ lbn, PairW<NKCN>& wn0,
@@ -204,7 +211,7 @@ __device__ __forceinline__ void layer_bf16(const uint4* __restrict__ wl, const f
         if constexpr (PEND && NKC == 1) {
             if (p == 0) {                        // no earlier chunk to hide the split behind
 #pragma unroll
-                for (int s = 0; s < NS; ++s) split_slice<NB, NKC, true>(s, pin, ZERO_IN, xh, xl, 0);
+                for (int s = 0; s < NS; ++s) split_slice<NB, NKC, true, LO>(s, pin, ZERO_IN, xh, xl, 0);
             }
         }
         // VALU work between this pair's MFMAs: in pair 0 the split of the
@@ -217,19 +224,19 @@ __device__ __forceinline__ void layer_bf16(const uint4* __restrict__ wl, const f
                     int s0, s1;
                     slices_of_slot<NS>(k, (two ? 2 : 1) * NB * (NKC - 1), s0, s1);
 #pragma unroll
-                    for (int s = s0; s < s1; ++s) split_slice<NB, NKC, true>(s, pin, ZERO_IN, xh, xl, NKC - 1);
+                    for (int s = s0; s < s1; ++s) split_slice<NB, NKC, true, LO>(s, pin, ZERO_IN, xh, xl, NKC - 1);
                 }
             } else if constexpr (!LAST) {
                 int s0, s1;
                 slices_of_slot<NS>(k, (two ? 2 : 1) * NB * NKC, s0, s1);
 #pragma unroll
-                for (int s = s0; s < s1; ++s) split_slice<NB, NKCN, true>(s, c[(p - 1) & 1], 8, nh, nl, p - 1);
+                for (int s = s0; s < s1; ++s) split_slice<NB, NKCN, true, LO>(s, c[(p - 1) & 1], 8, nh, nl, p - 1);
             }
         };
         if (two)
-            pair_mfma<NB, NKC, 2>(wb[p & 1], xh, xl, c[p & 1], slot);
+            pair_mfma<NB, NKC, 2, LO>(wb[p & 1], xh, xl, c[p & 1], slot);
         else
-            pair_mfma<NB, NKC, 1>(wb[p & 1], xh, xl, c[p & 1], slot);
+            pair_mfma<NB, NKC, 1, LO>(wb[p & 1], xh, xl, c[p & 1], slot);
         if constexpr (LAST) {
 #pragma unroll
             for (int j = 0; j < 2; ++j)
@@ -270,7 +277,11 @@ __device__ __forceinline__ void mlp_load_inputs(const MlpArgs& a, const float* _
 // Hidden layers l0 .. L-2 alternate between the two activation sets, so the
 // loop runs two layers per iteration; the last layer reads whichever set the
 // parity of L leaves.
-template <int MB, int NB>
+//
+// LO: activations as a bf16 hi + lo pair (about 16 significant bits, the
+// BF16 precision); without it bf16 alone (the FP8 precision, whose blur
+// error is far larger than what the lo part removes).
+template <int MB, int NB, bool LO = true>
 __device__ __forceinline__ void mlp_bf16_eval(const MlpArgs& a, const uint4* __restrict__ lds_w16,
                                               const float* __restrict__ bias, const float (&in)[NB][2][8],
                                               float (&out)[NB][MB][4]) {
@@ -293,29 +304,29 @@ __device__ __forceinline__ void mlp_bf16_eval(const MlpArgs& a, const uint4* __r
 #pragma unroll
             for (int e = 0; e < 8; ++e) v[e >> 2][nb][e & 3] = in[nb][kc][e];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) split_slice<NB, 2, false>(s, v, 8, x0h, x0l, kc);
+        for (int s = 0; s < NS; ++s) split_slice<NB, 2, false, LO>(s, v, 8, x0h, x0l, kc);
     }
     if (a.L == 1) {
-        layer_bf16<MB, NB, 2, NKC, false, true>(lds_w16 + a.woff[0], bias + a.boff[0], w00, nullptr, nullptr, wa, x0h,
+        layer_bf16<MB, NB, 2, NKC, false, true, LO>(lds_w16 + a.woff[0], bias + a.boff[0], w00, nullptr, nullptr, wa, x0h,
                                                 x0l, pa, ah, al, pb, o, lane);
     } else {
-        layer_bf16<MB, NB, 2, NKC, false, false>(lds_w16 + a.woff[0], bias + a.boff[0], w00, lds_w16 + a.woff[1],
+        layer_bf16<MB, NB, 2, NKC, false, false, LO>(lds_w16 + a.woff[0], bias + a.boff[0], w00, lds_w16 + a.woff[1],
                                                  bias + a.boff[1], wa, x0h, x0l, pb, ah, al, pa, o, lane);
         int l = 1;
         for (; l + 2 < a.L; l += 2) {
-            layer_bf16<MB, NB, NKC, NKC, true, false>(lds_w16 + a.woff[l], bias + a.boff[l], wa, lds_w16 + a.woff[l + 1],
+            layer_bf16<MB, NB, NKC, NKC, true, false, LO>(lds_w16 + a.woff[l], bias + a.boff[l], wa, lds_w16 + a.woff[l + 1],
                                                       bias + a.boff[l + 1], wb, ah, al, pa, bh, bl, pb, o, lane);
-            layer_bf16<MB, NB, NKC, NKC, true, false>(lds_w16 + a.woff[l + 1], bias + a.boff[l + 1], wb,
+            layer_bf16<MB, NB, NKC, NKC, true, false, LO>(lds_w16 + a.woff[l + 1], bias + a.boff[l + 1], wb,
                                                       lds_w16 + a.woff[l + 2], bias + a.boff[l + 2], wa, bh, bl, pb, ah,
                                                       al, pa, o, lane);
         }
         if (l + 1 < a.L) {                       // one hidden layer left, then the last
-            layer_bf16<MB, NB, NKC, NKC, true, false>(lds_w16 + a.woff[l], bias + a.boff[l], wa, lds_w16 + a.woff[l + 1],
+            layer_bf16<MB, NB, NKC, NKC, true, false, LO>(lds_w16 + a.woff[l], bias + a.boff[l], wa, lds_w16 + a.woff[l + 1],
                                                       bias + a.boff[l + 1], wb, ah, al, pa, bh, bl, pb, o, lane);
-            layer_bf16<MB, NB, NKC, NKC, true, true>(lds_w16 + a.woff[l + 1], bias + a.boff[l + 1], wb, nullptr, nullptr,
+            layer_bf16<MB, NB, NKC, NKC, true, true, LO>(lds_w16 + a.woff[l + 1], bias + a.boff[l + 1], wb, nullptr, nullptr,
                                                      wa, bh, bl, pb, ah, al, pa, o, lane);
         } else {
-            layer_bf16<MB, NB, NKC, NKC, true, true>(lds_w16 + a.woff[l], bias + a.boff[l], wa, nullptr, nullptr, wb, ah,
+            layer_bf16<MB, NB, NKC, NKC, true, true, LO>(lds_w16 + a.woff[l], bias + a.boff[l], wa, nullptr, nullptr, wb, ah,
                                                      al, pa, bh, bl, pb, o, lane);
         }
     }

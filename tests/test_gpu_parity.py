@@ -332,9 +332,11 @@ def test_simulate_workload(p2s, name, prec):
 
 @pytest.mark.parametrize("name", ["single128", "single512"])
 def test_simulate_fp8(p2s, name):
-    """FP8 blur (network in BF16) end to end: against the oracle with E4M3 blur
-    operands within the BF16 bound (the network's BF16 error dominates), and
-    the FP8 variant's own error against the exact oracle reported."""
+    """FP8 blur (network on BF16 MFMA with bf16 activations) end to end:
+    against the oracle with E4M3 blur operands, 5e-3 (what remains is the
+    network's activation rounding: unit roundoff 2^-9 at each of 3 layers,
+    about 2e-3 on w for a random network), and the FP8 variant's own error
+    against the exact oracle reported."""
     wl = S.workload(name)
     f = wl.frames[0]
     basis = oracle_basis(name)
@@ -345,7 +347,7 @@ def test_simulate_fp8(p2s, name):
     ref = osimulate(img, f.d_over_r0, basis, Ws, bs, seed=f.field_seed)["out"]
     eq, ee = rel_l2(got, ref_q), rel_l2(got, ref)
     print(f"\n{name} fp8 end-to-end rel-L2: vs E4M3-operand oracle {eq:.3e}, vs FP64 oracle {ee:.3e}")
-    assert eq < 3e-3
+    assert eq < 5e-3
     assert ee < 5e-2
 
 
@@ -438,7 +440,7 @@ def test_bf16_with_generic_fp32_weights(p2s):
     assert e_net < 5e-3 and e_sim < 1e-2, (e_net, e_sim)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 3e-3), ("fp8", 3e-3)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 3e-3), ("fp8", 5e-3)])
 def test_simulate_trained_network(p2s, prec, tol):
     """A whole 512x512 frame with the trained P2S network of that workload's
     basis (weights are data: the kernels are the same) against the oracle;
