@@ -5,8 +5,10 @@
  * One frame goes through four stages, each a call below and all four chained
  * by p2s_simulate:
  *   fields  -- per-pixel Zernike coefficient planes alpha_j(x), spatially
- *              correlated (Sec. 2.2 Eq. 1 and Sec. 3.4), here made by
- *              filtering seeded white noise with a Gaussian PSD;
+ *              correlated (Sec. 2.2 Eq. 1 and Sec. 3.4), made either by
+ *              filtering seeded white noise with a Gaussian PSD
+ *              (p2s_make_fields) or, as in the paper, drawn on a grid of
+ *              anchor points and interpolated (p2s_make_fields_anchor);
  *   mlp     -- the P2S network mapping alpha_4.. to the basis weights
  *              beta_m(x) at every pixel (Sec. 3.3);
  *   blur    -- the spatially varying blur written as M invariant
@@ -70,6 +72,7 @@ typedef enum {
 /* Opaque, immutable, device-resident handles; safe to share across streams. */
 typedef struct p2s_basis_s* p2s_basis_t;
 typedef struct p2s_mlp_s* p2s_mlp_t;
+typedef struct p2s_anchor_s* p2s_anchor_t;
 
 /* Optional parameters; pass NULL for the defaults shown. */
 typedef struct {
@@ -87,6 +90,7 @@ typedef struct {
 #define P2S_MAX_LAYERS 4
 #define P2S_MAX_SIDE 16384     /* H, W                                       */
 #define P2S_MAX_CHANNELS 4
+#define P2S_MAX_ANCHOR_GRID 128 /* anchor grid side G                       */
 
 int p2s_version(void);
 const char* p2s_last_error(void);
@@ -218,6 +222,62 @@ int p2s_simulate(const float* image, int C, int H, int W, double D_over_r0, int 
 int p2s_simulate_noalloc(const float* image, int C, int H, int W, double D_over_r0, int n_zernike,
                          p2s_basis_t basis, p2s_mlp_t mlp, uint64_t seed, p2s_precision precision,
                          const p2s_params* params, float* out, void* stream);
+
+/* ------------------------------------------------------- anchor grid --
+ * The paper's own field model (Sec. 3.4, "Interpolation across the grid",
+ * with the mode covariance R_Z of Sec. 2.2): the Zernike coefficients of a
+ * G x G grid of anchor points are drawn jointly,
+ *   A = L_s E L_Z^T (D/r0)^(5/6),
+ * with L_s (L_s^T) the anchor correlation matrix R_s, L_Z (L_Z^T) = R_Z per
+ * (D/r0)^(5/3) and E [G^2][n_zernike] standard normals, so that
+ * Cov(A[p][i], A[q][k]) = R_s[p][q] R_Z[i][k] (D/r0)^(5/3); then every plane
+ * is interpolated bilinearly from the anchors to the pixels (interpolation of
+ * the coefficients, i.e. of the phase, not of PSFs).  E[p][i] comes from
+ * Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter
+ * (p, i >> 1, 0, 1), Box-Muller on outputs 0 and 1 as for p2s_make_fields
+ * (cosine for even i, sine for odd i).  Anchor (a, b), index p = a G + b,
+ * sits at pixel (a (H-1)/(G-1), b (W-1)/(G-1)): the grid spans the image from
+ * corner to corner whatever its size, so the correlation is set in anchor
+ * spacings.  Both covariances are the caller's: the library takes their
+ * factors as data (any model, e.g. angle-of-arrival statistics, fits). */
+
+/* Upload the two factors.  host_spatial: host float64 [G*G][G*G],
+ * row-major, the lower-triangular L_s (entries above the diagonal are
+ * ignored); host_modes: host float64 [n_zernike][n_zernike], the
+ * lower-triangular L_Z for planes i = Noll mode i + 2 (above the diagonal
+ * ignored).  G in [2, P2S_MAX_ANCHOR_GRID], n_zernike in
+ * [1, P2S_MAX_ZERNIKE].  Both are read during the call only; the handle
+ * keeps FP32 copies, 4 Gp (Gp + 32) bytes of device memory for Gp = G^2
+ * rounded up to 32 (about 64 MiB for G = 64).  EINVAL on a non-finite entry. */
+int p2s_anchor_create(int G, int n_zernike, const double* host_spatial, const double* host_modes,
+                      p2s_anchor_t* out);
+int p2s_anchor_destroy(p2s_anchor_t anchors);
+int p2s_anchor_info(p2s_anchor_t anchors, int* G, int* n_zernike);
+
+/* Device bytes p2s_make_fields_anchor needs as workspace (the normals times
+ * L_Z^T, and the partial sums of the anchor product); 0 for NULL. */
+size_t p2s_anchor_fields_workspace_bytes(p2s_anchor_t anchors);
+
+/* Stage 1 with the anchor model: fields = device float32
+ * [n_zernike][H][W] (n_zernike of the handle; plane i = Noll mode i + 2),
+ * bilinear in every anchor cell.  ws: device, at least
+ * p2s_anchor_fields_workspace_bytes, must not overlap fields.  D/r0 finite
+ * and >= 0. */
+int p2s_make_fields_anchor(p2s_anchor_t anchors, int H, int W, double D_over_r0, uint64_t seed, float* fields,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace of p2s_simulate_anchor for a C x H x W frame and a basis of K
+ * functions; 0 on a bad argument. */
+size_t p2s_workspace_bytes_anchor(p2s_anchor_t anchors, int C, int H, int W, int K);
+
+/* One frame end to end with the anchor model as stage 1: otherwise exactly
+ * p2s_simulate (network and blur fused where that form applies, then the
+ * warp by planes 0 and 1).  The handle's n_zernike - 2 must equal the
+ * network's input width; params: only q_sampling is used.  ws: at least
+ * p2s_workspace_bytes_anchor. */
+int p2s_simulate_anchor(const float* image, int C, int H, int W, double D_over_r0, p2s_anchor_t anchors,
+                        p2s_basis_t basis, p2s_mlp_t mlp, uint64_t seed, p2s_precision precision,
+                        const p2s_params* params, float* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------- batches --
  * Many frames, of any sizes and channel counts, through the same four stages

@@ -6,23 +6,34 @@ every channel with alpha_2, alpha_3.
 ``weights="projection"`` replaces the network by the projection of each
 pixel's exact PSF onto the basis (used to measure truncation error),
 ``exact_blur`` adds the per-pixel pupil-FFT blur of Eq. 3 (tiny frames only),
-and ``blur_operands="fp8"`` feeds the basis blur E4M3-rounded image and basis
-values (the FP8 precision variant; everything else unchanged).
+``blur_operands="fp8"`` feeds the basis blur E4M3-rounded image and basis
+values (the FP8 precision variant; everything else unchanged), and
+``field_model="anchor"`` draws the fields on a G x G anchor grid and
+interpolates them (Sec. 3.4, ``anchors``) instead of FFT filtering.
 """
 import numpy as np
 
-from . import blur, fields, fp8, mlp, psf, warp
+from . import anchors, blur, fields, fp8, mlp, psf, warp
+
+
+def _fields(H, W, d_over_r0, n_zernike, seed, corr_len, field_model, G, anchor_corr):
+    if field_model == "fft":
+        return fields.make_fields(H, W, d_over_r0, n_zernike, seed, corr_len)
+    if field_model == "anchor":
+        return anchors.make_fields(H, W, d_over_r0, n_zernike, seed, G, anchor_corr)
+    raise ValueError(field_model)
 
 
 def simulate(image: np.ndarray, d_over_r0: float, basis: np.ndarray, Ws=None, bs=None, seed: int = 0,
              n_zernike: int = 35, corr_len: float = 16.0, q: float = 2.0,
-             weights: str = "mlp", exact: bool = False, Np: int = 32, blur_operands: str = "exact"):
+             weights: str = "mlp", exact: bool = False, Np: int = 32, blur_operands: str = "exact",
+             field_model: str = "fft", G: int = 64, anchor_corr: float = 2.0):
     img = np.asarray(image, dtype=np.float64)
     if img.ndim == 2:
         img = img[None]
     C, H, W = img.shape
     K, P, _ = basis.shape
-    F = fields.make_fields(H, W, d_over_r0, n_zernike, seed, corr_len)
+    F = _fields(H, W, d_over_r0, n_zernike, seed, corr_len, field_model, G, anchor_corr)
     alpha_hi = np.moveaxis(F[2:], 0, -1).reshape(H * W, n_zernike - 2)      # [pix][j=4..]
     res = {"fields": F}
     psfs = None
@@ -51,7 +62,8 @@ def simulate(image: np.ndarray, d_over_r0: float, basis: np.ndarray, Ws=None, bs
 
 
 def simulate_pixels(image: np.ndarray, d_over_r0: float, basis: np.ndarray, Ws, bs, seed: int, pixels,
-                    n_zernike: int = 35, corr_len: float = 16.0, q: float = 2.0) -> np.ndarray:
+                    n_zernike: int = 35, corr_len: float = 16.0, q: float = 2.0, field_model: str = "fft",
+                    G: int = 64, anchor_corr: float = 2.0) -> np.ndarray:
     """simulate()["out"] at chosen output pixels only, for frames too large
     to blur whole on the host.  The same steps, evaluated where they are
     needed: the fields in full; then for each output pixel (c, y, x) its tilt
@@ -69,7 +81,7 @@ def simulate_pixels(image: np.ndarray, d_over_r0: float, basis: np.ndarray, Ws, 
     K, P, _ = basis.shape
     R = (P - 1) // 2
     B = np.asarray(basis, dtype=np.float64)
-    F = fields.make_fields(H, W, d_over_r0, n_zernike, seed, corr_len)
+    F = _fields(H, W, d_over_r0, n_zernike, seed, corr_len, field_model, G, anchor_corr)
     dx = warp.displacement(F[0], q)
     dy = warp.displacement(F[1], q)
     offs = np.arange(P) - R

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libp2s.so")
-SOURCES = ["api.hip", "fields.hip", "mlp.hip", "blur.hip", "warp.hip"]
+SOURCES = ["api.hip", "fields.hip", "anchors.hip", "mlp.hip", "blur.hip", "warp.hip"]
 ARCH = os.environ.get("P2S_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -20,6 +20,9 @@ struct p2s_basis_s {
 struct p2s_mlp_s {
     p2s::Mlp m;
 };
+struct p2s_anchor_s {
+    p2s::Anchor a;
+};
 
 
 namespace p2s {
@@ -198,6 +201,54 @@ int make_fields_impl(int H, int W, double d, int nz, uint64_t seed, const Params
     if (ws_bytes < need) return fail(P2S_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     hipError_t e = launch_fields(fp, (float*)ws, F, s);
     if (e != hipSuccess) return hip_fail(e, "field kernels");
+    return P2S_OK;
+}
+
+int anchor_fields_impl(const Anchor& an, int H, int W, double d, uint64_t seed, float* F, void* ws,
+                       size_t ws_bytes, hipStream_t s) {
+    if (H < 1 || W < 1 || H > P2S_MAX_SIDE || W > P2S_MAX_SIDE)
+        return fail(P2S_EINVAL, "H, W must be in [1, %d], got %d x %d", P2S_MAX_SIDE, H, W);
+    if (!(std::isfinite(d) && d >= 0.0)) return fail(P2S_EINVAL, "D/r0 must be finite and >= 0");
+    if (!F) return fail(P2S_EINVAL, "fields is NULL");
+    if (!ws) return fail(P2S_EINVAL, "workspace is NULL");
+    const size_t need = anchor_ws_bytes(an);
+    if (ws_bytes < need) return fail(P2S_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    if (overlap(ws, need, F, (size_t)an.n * H * W * 4)) return fail(P2S_EINVAL, "workspace and fields overlap");
+    hipError_t e = launch_anchor_fields(an, H, W, d, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), F, ws, s);
+    if (e != hipSuccess) return hip_fail(e, "anchor field kernels");
+    return P2S_OK;
+}
+
+int pack_anchor(int G, int n, const double* Ls, const double* Lz, Anchor* out) {
+    Anchor an;
+    an.G = G;
+    an.n = n;
+    an.Gp = (G * G + 31) / 32 * 32;
+    an.ld = an.Gp + 32;
+    an.nct = (n + 15) / 16;
+    an.Ls = nullptr;
+    an.Lz = nullptr;
+    const size_t G2 = (size_t)G * G, Gp = an.Gp, ld = an.ld;
+    std::vector<float> hs(Gp * ld, 0.0f), hz((size_t)n * n, 0.0f);
+    for (size_t r = 0; r < G2; ++r)
+        for (size_t c = 0; c <= r; ++c) hs[r * ld + c] = (float)Ls[r * G2 + c];
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c <= r; ++c) hz[(size_t)r * n + c] = (float)Lz[(size_t)r * n + c];
+    hipError_t e = hipMalloc((void**)&an.Ls, hs.size() * 4);
+    if (e != hipSuccess) return fail(P2S_ENOMEM, "device allocation of %zu bytes failed", hs.size() * 4);
+    e = hipMalloc((void**)&an.Lz, hz.size() * 4);
+    if (e != hipSuccess) {
+        (void)hipFree(an.Ls);
+        return fail(P2S_ENOMEM, "device allocation failed");
+    }
+    e = hipMemcpy(an.Ls, hs.data(), hs.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(an.Lz, hz.data(), hz.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(an.Ls);
+        (void)hipFree(an.Lz);
+        return hip_fail(e, "upload of the anchor factors");
+    }
+    *out = an;
     return P2S_OK;
 }
 
@@ -427,16 +478,20 @@ struct SimLayout {
 // with_w: the second region also holds the network output w (the path that
 // runs the network and the blur as two kernels); without it, only the field
 // generator's intermediate.
-SimLayout sim_layout(int C, int H, int W, int nz, int K, const Params& pr, bool with_w = true) {
+SimLayout sim_layout_fws(int C, int H, int W, int nz, int K, size_t fws, bool with_w) {
     SimLayout L;
     const size_t HW = (size_t)H * W;
     L.fields = 0;
     const size_t fb = align256((size_t)nz * HW * 4);
-    const size_t r2 = with_w ? std::max(fields_ws(H, W, nz, pr), align256(HW * K * 4)) : fields_ws(H, W, nz, pr);
+    const size_t r2 = with_w ? std::max(align256(fws), align256(HW * K * 4)) : align256(fws);
     L.region2 = fb;
     L.blurred = fb + r2;
     L.total = L.blurred + align256((size_t)C * HW * 4);
     return L;
+}
+
+SimLayout sim_layout(int C, int H, int W, int nz, int K, const Params& pr, bool with_w = true) {
+    return sim_layout_fws(C, H, W, nz, K, fields_ws(H, W, nz, pr), with_w);
 }
 
 // ---------------------------------------------------------------- batches
@@ -737,7 +792,7 @@ namespace {
 // must hold p2s_workspace_bytes.
 int simulate_impl(const float* image, int C, int H, int W, double D_over_r0, int n_zernike, p2s_basis_t basis,
                   p2s_mlp_t mlp, uint64_t seed, p2s_precision precision, const p2s_params* params, float* out,
-                  void* ws, size_t ws_bytes, bool use_scratch, hipStream_t s) {
+                  void* ws, size_t ws_bytes, bool use_scratch, hipStream_t s, const Anchor* anc = nullptr) {
     Params pr;
     int rc = read_params(params, &pr);
     if (rc) return rc;
@@ -759,10 +814,11 @@ int simulate_impl(const float* image, int C, int H, int W, double D_over_r0, int
     if (!image || !out || (!use_scratch && !ws)) return fail(P2S_EINVAL, "image, out or workspace is NULL");
     if (!(std::isfinite(D_over_r0) && D_over_r0 >= 0.0)) return fail(P2S_EINVAL, "D/r0 must be finite and >= 0");
     const int Nfy = grid_of(H, pr.corr_len), Nfx = grid_of(W, pr.corr_len);
-    if (Nfy > kMaxFftLen || Nfx > kMaxFftLen)
+    if (!anc && (Nfy > kMaxFftLen || Nfx > kMaxFftLen))
         return fail(P2S_EUNSUPPORTED, "noise grid %d x %d exceeds the single-workgroup FFT limit %d", Nfy, Nfx, kMaxFftLen);
     const bool fused = blur_mlp_supported(basis->b, mlp->m, precision);
-    const SimLayout L = sim_layout(C, H, W, n_zernike, basis->b.K, pr, !use_scratch || !fused);
+    const size_t fws = anc ? anchor_ws_bytes(*anc) : fields_ws(H, W, n_zernike, pr);
+    const SimLayout L = sim_layout_fws(C, H, W, n_zernike, basis->b.K, fws, !use_scratch || !fused);
     if (use_scratch) {
         if (L.total > kScratchBytes)
             return fail(P2S_EINVAL, "frame needs %zu bytes of intermediates, more than the %zu-byte device scratch",
@@ -781,7 +837,8 @@ int simulate_impl(const float* image, int C, int H, int W, double D_over_r0, int
     float* F = (float*)(base + L.fields);
     float* r2 = (float*)(base + L.region2);
     float* bl = (float*)(base + L.blurred);
-    rc = make_fields_impl(H, W, D_over_r0, n_zernike, seed, pr, F, r2, L.blurred - L.region2, s);
+    rc = anc ? anchor_fields_impl(*anc, H, W, D_over_r0, seed, F, r2, L.blurred - L.region2, s)
+             : make_fields_impl(H, W, D_over_r0, n_zernike, seed, pr, F, r2, L.blurred - L.region2, s);
     if (rc) return rc;
     if (fused) {     // w never leaves the chip
         hipError_t e = launch_blur_mlp(basis->b, mlp->m, precision, image, C, H, W, F, bl, s);
@@ -1005,6 +1062,76 @@ int p2s_simulate_noalloc(const float* image, int C, int H, int W, double D_over_
                          const p2s_params* params, float* out, void* stream) {
     return simulate_impl(image, C, H, W, D_over_r0, n_zernike, basis, mlp, seed, precision, params, out, nullptr,
                          0, true, (hipStream_t)stream);
+}
+
+int p2s_anchor_create(int G, int n_zernike, const double* host_spatial, const double* host_modes,
+                      p2s_anchor_t* out) {
+    try {
+        if (!host_spatial || !host_modes || !out) return fail(P2S_EINVAL, "host_spatial, host_modes or out is NULL");
+        if (G < 2 || G > P2S_MAX_ANCHOR_GRID)
+            return fail(P2S_EINVAL, "G must be in [2, %d], got %d", P2S_MAX_ANCHOR_GRID, G);
+        if (n_zernike < 1 || n_zernike > P2S_MAX_ZERNIKE)
+            return fail(P2S_EINVAL, "n_zernike must be in [1, %d], got %d", P2S_MAX_ZERNIKE, n_zernike);
+        const size_t G2 = (size_t)G * G;
+        for (size_t r = 0; r < G2; ++r)
+            for (size_t c = 0; c <= r; ++c)
+                if (!std::isfinite(host_spatial[r * G2 + c]))
+                    return fail(P2S_EINVAL, "spatial factor entry (%zu, %zu) is not finite", r, c);
+        for (int r = 0; r < n_zernike; ++r)
+            for (int c = 0; c <= r; ++c)
+                if (!std::isfinite(host_modes[(size_t)r * n_zernike + c]))
+                    return fail(P2S_EINVAL, "mode factor entry (%d, %d) is not finite", r, c);
+        auto* h = new (std::nothrow) p2s_anchor_s();
+        if (!h) return fail(P2S_ENOMEM, "host allocation failed");
+        int rc = pack_anchor(G, n_zernike, host_spatial, host_modes, &h->a);
+        if (rc) {
+            delete h;
+            return rc;
+        }
+        *out = h;
+        return ok();
+    } catch (...) {
+        return fail(P2S_ENOMEM, "host allocation failed");
+    }
+}
+
+int p2s_anchor_destroy(p2s_anchor_t anchors) {
+    if (!anchors) return ok();
+    (void)hipFree(anchors->a.Ls);
+    (void)hipFree(anchors->a.Lz);
+    delete anchors;
+    return ok();
+}
+
+int p2s_anchor_info(p2s_anchor_t anchors, int* G, int* n_zernike) {
+    if (!anchors) return fail(P2S_EINVAL, "anchors is NULL");
+    if (G) *G = anchors->a.G;
+    if (n_zernike) *n_zernike = anchors->a.n;
+    return ok();
+}
+
+size_t p2s_anchor_fields_workspace_bytes(p2s_anchor_t anchors) {
+    return anchors ? anchor_ws_bytes(anchors->a) : 0;
+}
+
+int p2s_make_fields_anchor(p2s_anchor_t anchors, int H, int W, double D_over_r0, uint64_t seed, float* fields,
+                           void* ws, size_t ws_bytes, void* stream) {
+    if (!anchors) return fail(P2S_EINVAL, "anchors is NULL");
+    int rc = anchor_fields_impl(anchors->a, H, W, D_over_r0, seed, fields, ws, ws_bytes, (hipStream_t)stream);
+    return rc ? rc : ok();
+}
+
+size_t p2s_workspace_bytes_anchor(p2s_anchor_t anchors, int C, int H, int W, int K) {
+    if (!anchors || check_frame(C, H, W) || K < 1 || K > P2S_MAX_K) return 0;
+    return sim_layout_fws(C, H, W, anchors->a.n, K, anchor_ws_bytes(anchors->a), true).total;
+}
+
+int p2s_simulate_anchor(const float* image, int C, int H, int W, double D_over_r0, p2s_anchor_t anchors,
+                        p2s_basis_t basis, p2s_mlp_t mlp, uint64_t seed, p2s_precision precision,
+                        const p2s_params* params, float* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!anchors) return fail(P2S_EINVAL, "anchors is NULL");
+    return simulate_impl(image, C, H, W, D_over_r0, anchors->a.n, basis, mlp, seed, precision, params, out, ws,
+                         ws_bytes, false, (hipStream_t)stream, &anchors->a);
 }
 
 size_t p2s_batch_workspace_bytes(const p2s_frame* frames, int n, int n_zernike, int K, const p2s_params* params) {

@@ -34,28 +34,6 @@ __device__ __forceinline__ float2 mul_i(float2 a, float sgn) {   // sgn * i * a
     return make_float2(-sgn * a.y, sgn * a.x);
 }
 
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 bit
-// products on words 0 and 2, key advanced by the Weyl constants between
-// rounds.
-__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
-                                              uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int i = 0; i < 10; ++i) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
 // Complex standard normal of bin (ky, kx) of plane pair q: counter
 // (kx, ky, q, 0), Box-Muller on outputs 0 and 1.
 __device__ __forceinline__ float2 bin_noise(int kx, int ky, int q, uint32_t k0, uint32_t k1,
@@ -68,12 +46,7 @@ __device__ __forceinline__ float2 bin_noise(int kx, int ky, int q, uint32_t k0, 
         raw_out[2] = c2;
         raw_out[3] = c3;
     }
-    const float two24 = 5.9604644775390625e-08f;   // 2^-24
-    const float ua = (float)((c0 >> 8) + 1u) * two24, ub = (float)(c1 >> 8) * two24;
-    const float r = sqrtf(-2.0f * logf(ua));
-    float s, c;
-    sincospif(2.0f * ub, &s, &c);
-    return make_float2(r * c, r * s);
+    return box_muller(c0, c1);
 }
 
 // Band index of an FFT bin (bins 0..kc and N-(M-1-kc)..N-1 hold band

@@ -68,6 +68,19 @@ struct Mlp {
     int boff[P2S_MAX_LAYERS];
 };
 
+// Device copy of the anchor-grid field model: the lower Cholesky factors of
+// the anchor correlation matrix (FP32 [Gp][ld], row-major, zero above the
+// diagonal and in the padding rows and columns; Gp = G^2 rounded up to 32, and
+// the row stride ld = Gp + 32 so that the rows of a tile, read together, do
+// not all fall on a power-of-two stride) and of the mode covariance per
+// (D/r0)^(5/3) (FP32 [n][n], zero above the diagonal).  nct = ceil(n / 16)
+// column tiles of the product.
+struct Anchor {
+    int G, n, Gp, ld, nct;
+    float* Ls;
+    float* Lz;
+};
+
 // Packed network weights are staged in the LDS of one workgroup.
 constexpr size_t kMlpLdsBytes = 160 * 1024;
 
@@ -174,12 +187,54 @@ hipError_t launch_blur_mlp(const Basis& b, const Mlp& m, p2s_precision prec, con
 hipError_t launch_blur_mlp_batch(const Basis& b, const Mlp& m, const BatchLaunch& bl, p2s_precision prec,
                                  hipStream_t s);
 
+// Anchor-grid fields: noise, triangular product and interpolation on stream s;
+// ws holds anchor_ws_bytes.  anchor_window_cols: anchor columns one segment of
+// seg pixels of a W-wide image touches (its LDS window is 2 rows of them).
+int anchor_window_cols(int G, int W, int seg);
+size_t anchor_ws_bytes(const Anchor& an);
+hipError_t launch_anchor_fields(const Anchor& an, int H, int W, double D_over_r0, uint32_t k0, uint32_t k1,
+                                float* fields, void* ws, hipStream_t s);
+
 // --------------------------------------------------------- host helpers
 uint16_t f32_to_bf16_rne(float x);
 uint8_t f32_to_e4m3_rne(float x);     // OCP E4M3, ties to even, |x| clamped to 448
 int e4m3_scale_exponent(float amax);  // largest e with amax 2^e <= 448 (0 for 0), within +-127
 
 // ------------------------------------------------------- device helpers
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 bit
+// products on words 0 and 2, key advanced by the Weyl constants between
+// rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                              uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Box-Muller pair from two Philox outputs: u_a = ((o0 >> 8) + 1) 2^-24 in
+// (0, 1], u_b = (o1 >> 8) 2^-24 in [0, 1) (both exact in FP32);
+// returns sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b).
+__device__ __forceinline__ float2 box_muller(uint32_t o0, uint32_t o1) {
+    const float two24 = 5.9604644775390625e-08f;   // 2^-24
+    const float ua = (float)((o0 >> 8) + 1u) * two24, ub = (float)(o1 >> 8) * two24;
+    const float r = sqrtf(-2.0f * logf(ua));
+    float s, c;
+    sincospif(2.0f * ub, &s, &c);
+    return make_float2(r * c, r * s);
+}
+
 __device__ __forceinline__ uint32_t bf16_bits_rne(float x) {
     uint32_t u = __float_as_uint(x);
     u += 0x7FFFu + ((u >> 16) & 1u);

@@ -28,7 +28,9 @@ EXPORTS = [
     "p2s_mlp_info", "p2s_make_fields", "p2s_mlp", "p2s_blur", "p2s_mlp_blur", "p2s_warp",
     "p2s_simulate", "p2s_debug_noise", "p2s_batch_workspace_bytes", "p2s_batch_create",
     "p2s_batch_upload", "p2s_batch_launch", "p2s_batch_info", "p2s_batch_destroy", "p2s_simulate_batch",
-    "p2s_simulate_noalloc",
+    "p2s_simulate_noalloc", "p2s_anchor_create", "p2s_anchor_destroy", "p2s_anchor_info",
+    "p2s_anchor_fields_workspace_bytes", "p2s_make_fields_anchor", "p2s_workspace_bytes_anchor",
+    "p2s_simulate_anchor",
 ]
 
 
@@ -96,8 +98,17 @@ def lib():
         L.p2s_batch_info.argtypes = [vp, C.POINTER(i), C.POINTER(i)]
         L.p2s_batch_destroy.argtypes = [vp]
         L.p2s_simulate_batch.argtypes = [vp, i, i, vp, vp, i, vp, vp, sz, vp]
+        L.p2s_anchor_create.argtypes = [i, i, vp, vp, C.POINTER(vp)]
+        L.p2s_anchor_destroy.argtypes = [vp]
+        L.p2s_anchor_info.argtypes = [vp, C.POINTER(i), C.POINTER(i)]
+        L.p2s_anchor_fields_workspace_bytes.argtypes = [vp]
+        L.p2s_anchor_fields_workspace_bytes.restype = sz
+        L.p2s_make_fields_anchor.argtypes = [vp, i, i, d, u64, vp, vp, sz, vp]
+        L.p2s_workspace_bytes_anchor.argtypes = [vp, i, i, i, i]
+        L.p2s_workspace_bytes_anchor.restype = sz
+        L.p2s_simulate_anchor.argtypes = [vp, i, i, i, d, vp, vp, vp, u64, i, vp, vp, vp, sz, vp]
         sized = ("p2s_version", "p2s_last_error", "p2s_fields_workspace_bytes", "p2s_workspace_bytes",
-                 "p2s_batch_workspace_bytes")
+                 "p2s_batch_workspace_bytes", "p2s_anchor_fields_workspace_bytes", "p2s_workspace_bytes_anchor")
         for name in EXPORTS:
             if name not in sized:
                 getattr(L, name).restype = i
@@ -225,7 +236,61 @@ class Mlp:
             pass
 
 
+class Anchors:
+    """Device-resident anchor-grid field model (p2s_anchor_create): the
+    lower Cholesky factors of the anchor correlation matrix [G^2][G^2] and of
+    the mode covariance [n][n] per (D/r0)^(5/3)."""
+
+    def __init__(self, G: int, spatial_factor: np.ndarray, mode_factor: np.ndarray):
+        Ls = np.ascontiguousarray(spatial_factor, dtype=np.float64)
+        Lz = np.ascontiguousarray(mode_factor, dtype=np.float64)
+        if Ls.shape != (G * G, G * G):
+            raise ValueError(f"spatial factor must be [{G * G}][{G * G}], got {Ls.shape}")
+        if Lz.ndim != 2 or Lz.shape[0] != Lz.shape[1]:
+            raise ValueError("mode factor must be square")
+        self.G, self.n_zernike = int(G), int(Lz.shape[0])
+        h = C.c_void_p()
+        _check(lib().p2s_anchor_create(self.G, self.n_zernike, Ls.ctypes.data_as(C.c_void_p),
+                                       Lz.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self.handle = h
+
+    def fields_workspace_bytes(self) -> int:
+        return lib().p2s_anchor_fields_workspace_bytes(self.handle)
+
+    def workspace_bytes(self, C_: int, H: int, W: int, K: int) -> int:
+        return lib().p2s_workspace_bytes_anchor(self.handle, C_, H, W, K)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().p2s_anchor_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ---------------------------------------------------------------- compute
+def make_fields_anchor(anchors: Anchors, H, W, d_over_r0, seed, fields, ws, stream=None):
+    import torch
+    _check(lib().p2s_make_fields_anchor(anchors.handle, H, W, float(d_over_r0), int(seed) & (2 ** 64 - 1),
+                                        _ptr(fields, torch.float32, (anchors.n_zernike, H, W), "fields"),
+                                        _ptr(ws, name="ws"), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def simulate_anchor(image, d_over_r0, anchors: Anchors, basis: Basis, net: Mlp, seed, precision, out, ws,
+                    q_sampling=2.0, stream=None):
+    import torch
+    C_, H, W = image.shape
+    _check(lib().p2s_simulate_anchor(_ptr(image, torch.float32, None, "image"), C_, H, W, float(d_over_r0),
+                                     anchors.handle, basis.handle, net.handle, int(seed) & (2 ** 64 - 1),
+                                     _prec(precision), _params(16.0, q_sampling),
+                                     _ptr(out, torch.float32, (C_, H, W), "out"),
+                                     _ptr(ws, name="ws"), ws.numel() * ws.element_size(), _stream(stream)))
+
+
 def make_fields(H, W, d_over_r0, n_zernike, seed, fields, ws, corr_len_px=16.0, stream=None):
     import torch
     _check(lib().p2s_make_fields(H, W, float(d_over_r0), n_zernike, int(seed) & (2 ** 64 - 1),

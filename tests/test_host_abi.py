@@ -149,3 +149,50 @@ def test_product_basis_learner_matches_oracle():
     for k in range(12):
         if (k == 0 or gaps[k - 1] > 1e-6) and (k == 11 or gaps[k] > 1e-6):
             np.testing.assert_allclose(Bp[k], Bo[k], atol=1e-9)
+
+
+def test_anchor_validation_without_device(p2s):
+    """p2s_anchor_create rejects a bad grid, a bad mode count and non-finite
+    factor entries before any device allocation; NULL handles are refused by
+    the compute calls; the workspace queries return 0 for NULL."""
+    lib = p2s.lib()
+    G, n = 3, 5
+    Ls = np.eye(G * G)
+    Lz = np.eye(n)
+    h = C.c_void_p()
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    for g in (1, 0, 129):
+        assert lib.p2s_anchor_create(g, n, ptr(np.eye(max(g, 1) ** 2)), ptr(Lz), C.byref(h)) == p2s.P2S_EINVAL
+    for nz in (0, 65):
+        assert lib.p2s_anchor_create(G, nz, ptr(Ls), ptr(np.eye(max(nz, 1))), C.byref(h)) == p2s.P2S_EINVAL
+    bad = Ls.copy()
+    bad[4, 2] = np.nan
+    assert lib.p2s_anchor_create(G, n, ptr(bad), ptr(Lz), C.byref(h)) == p2s.P2S_EINVAL
+    assert b"not finite" in lib.p2s_last_error()
+    bad = Ls.copy()
+    bad[2, 4] = np.nan                     # above the diagonal: ignored, so only the next check fails
+    badz = Lz.copy()
+    badz[3, 1] = np.inf
+    assert lib.p2s_anchor_create(G, n, ptr(bad), ptr(badz), C.byref(h)) == p2s.P2S_EINVAL
+    assert b"mode factor" in lib.p2s_last_error()
+    assert lib.p2s_anchor_create(G, n, None, ptr(Lz), C.byref(h)) == p2s.P2S_EINVAL
+    assert lib.p2s_make_fields_anchor(None, 8, 8, 1.0, 0, None, None, 0, None) == p2s.P2S_EINVAL
+    assert lib.p2s_simulate_anchor(None, 1, 8, 8, 1.0, None, None, None, 0, 0, None, None, None, 0,
+                                   None) == p2s.P2S_EINVAL
+    assert lib.p2s_anchor_fields_workspace_bytes(None) == 0
+    assert lib.p2s_workspace_bytes_anchor(None, 1, 8, 8, 16) == 0
+    assert lib.p2s_anchor_destroy(None) == p2s.P2S_OK
+
+
+def test_product_anchor_setup_matches_oracle():
+    """The product's set-up of the anchor model (its own Noll indexing,
+    covariance and correlation code) equals the oracle's matrices."""
+    from oracle import anchors as oanch
+    from oracle import zernike as ozern
+    from paper_2107_11627_amd import anchors as panch
+    assert all(panch._noll_nm(j) == ozern.noll_to_nm(j) for j in range(1, 500))
+    for n in (1, 10, 35, 64):
+        a, b = panch.mode_covariance(n), oanch.mode_covariance(n)
+        assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
+    for G, l in ((2, 1.0), (7, 2.0), (12, 3.5)):
+        assert np.max(np.abs(panch.anchor_correlation(G, l) - oanch.anchor_correlation(G, l))) < 1e-15
