@@ -35,6 +35,8 @@ PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP8_TFLOPS = 5000.0
 PEAK_HBM_GBS = 8000.0
+ANCHOR_GRID = 64        # anchor grid side of the anchor-model frames (the paper's example)
+ANCHOR_CORR = 2.0       # anchor correlation length, in anchor spacings
 
 
 def log(*a):
@@ -113,6 +115,77 @@ def fields_mode(args, torch, p2s, fr, NZ, H, W):
     us = e0.elapsed_time(e1) * 1e3 / args.steps
     print(json.dumps({"mode": "fields", "avg_us": us, "output_bytes": 4 * NZ * H * W,
                       "GBps_output": 4 * NZ * H * W / us / 1e3}), flush=True)
+
+
+def anchor_fields_mode(args, torch, p2s, fr, NZ, H, W):
+    """Only the anchor-grid field generator (64 x 64 anchors), args.steps calls."""
+    from paper_2107_11627_amd import anchors as panch
+    model = panch.anchor_model(ANCHOR_GRID, NZ, ANCHOR_CORR)
+    F = torch.empty((NZ, H, W), dtype=torch.float32, device="cuda")
+    aws = torch.empty(model.fields_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    for i in range(args.warmup):
+        p2s.make_fields_anchor(model, H, W, fr.d_over_r0, 1000 + i, F, aws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(args.steps):
+        p2s.make_fields_anchor(model, H, W, fr.d_over_r0, 2000 + i, F, aws)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / args.steps
+    print(json.dumps({"mode": "anchor_fields", "avg_us": us, "grid": ANCHOR_GRID,
+                      "product_flops": anchor_product_flops(ANCHOR_GRID, NZ), "output_bytes": 4 * NZ * H * W}),
+          flush=True)
+
+
+def anchor_product_flops(G, n):
+    """Algorithmic flops of the anchor product L_s B: the lower triangle of the
+    G^2 x G^2 factor times n columns, one multiply-add each."""
+    return G * G * (G * G + 1) // 2 * n * 2
+
+
+def anchor_section(args, torch, p2s, sim, img, fr, NZ, H, W, C, stream):
+    """Frames with the paper's own field model: the Zernike coefficients of a
+    64 x 64 anchor grid drawn from the 4096 x 4096 correlation matrix (with
+    Noll's full R_Z) and interpolated to every pixel, then the same network,
+    blur and warp.  Throughput in BF16, the field generator's own time, and
+    one output kept for the oracle."""
+    from paper_2107_11627_amd import anchors as panch
+    t0 = time.perf_counter()
+    model = panch.anchor_model(ANCHOR_GRID, NZ, ANCHOR_CORR)
+    setup_s = time.perf_counter() - t0
+    aws = torch.empty(model.workspace_bytes(C, H, W, sim.basis.K), dtype=torch.uint8, device="cuda")
+    fws = torch.empty(model.fields_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(img)
+    F = torch.empty((NZ, H, W), dtype=torch.float32, device="cuda")
+
+    def timed(fn, n):
+        for i in range(args.warmup):
+            fn(1000 + i)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(n):
+            fn(3000 + i)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / n
+
+    fields_us = timed(lambda sd: p2s.make_fields_anchor(model, H, W, fr.d_over_r0, sd, F, fws), args.steps)
+    res = {"grid": ANCHOR_GRID, "correlation_length_anchor_spacings": ANCHOR_CORR, "host_setup_s": setup_s,
+           "fields_us": fields_us,
+           "product_flops": anchor_product_flops(ANCHOR_GRID, NZ)}
+    for prec in ("bf16", "fp32"):
+        us = timed(lambda sd: p2s.simulate_anchor(img, fr.d_over_r0, model, sim.basis, sim.net, sd, prec, out, aws),
+                   args.steps)
+        res[prec] = {"frames_per_s": 1e6 / us, "ms_per_frame": us / 1e3}
+    p2s.simulate_anchor(img, fr.d_over_r0, model, sim.basis, sim.net, fr.field_seed, "bf16", out, aws)
+    torch.cuda.synchronize()
+    kept = out.cpu().numpy().astype(np.float64)
+    log(f"[bench] anchor fields ({ANCHOR_GRID}x{ANCHOR_GRID} grid): {fields_us:.1f} us per field set; frames "
+        f"BF16 {res['bf16']['frames_per_s']:.0f}/s, FP32 {res['fp32']['frames_per_s']:.0f}/s")
+    model.close()
+    return res, kept
 
 
 def mlp_blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C, dims):
@@ -504,9 +577,12 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-slots", type=int, default=2)
     ap.add_argument("--serving-max-batch", type=int, default=16)
-    ap.add_argument("--mode", choices=["frame", "blur", "mlp", "mlp_blur", "pipeline", "fields", "warp", "copy"],
+    ap.add_argument("--no-anchors", action="store_true")
+    ap.add_argument("--mode", choices=["frame", "blur", "mlp", "mlp_blur", "pipeline", "fields", "anchor_fields",
+                                       "warp", "copy"],
                     default="frame",
-                    help="frame: the benchmark; blur / mlp / mlp_blur / fields / warp: only that kernel of the "
+                    help="frame: the benchmark; blur / mlp / mlp_blur / fields / anchor_fields / warp: only that "
+                         "kernel of the "
                          "workload (for counter runs); pipeline: the network-and-blur kernel timed inside "
                          "back-to-back frames (the benchmark's roofline timing); "
                          "copy: a plain device copy of known size (calibrates byte counters)")
@@ -552,6 +628,8 @@ def main():
         return blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C)
     if args.mode == "fields":
         return fields_mode(args, torch, p2s, fr, NZ, H, W)
+    if args.mode == "anchor_fields":
+        return anchor_fields_mode(args, torch, p2s, fr, NZ, H, W)
     if args.mode == "mlp_blur":
         return mlp_blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C, wl.mlp_dims)
     if args.mode == "pipeline":
@@ -666,6 +744,8 @@ def main():
                 "peak": PEAK_FP8_TFLOPS, "frac": (flops + nflops) / fp8_s / 1e12 / PEAK_FP8_TFLOPS,
                 "note": "the network's share runs on BF16 MFMA (peak 2500)"}
 
+    anchor, anchor_out = (None, None) if args.no_anchors else anchor_section(args, torch, p2s, sim, img, fr, NZ, H,
+                                                                              W, C, stream)
     batches, batch_samples = (None, {}) if args.no_batches else batch_section(args, torch, p2s, S, pbasis, ptrain)
     serving, serving_samples = (None, None) if args.no_serving else serving_section(args, torch, p2s, S, pbasis, ptrain)
 
@@ -715,7 +795,18 @@ def main():
             serving["oracle_worst_rel_l2_bf16"] = max(c["rel_l2_bf16"] for c in checked)
             log(f"[bench] serving: worst BF16 rel-L2 vs oracle over {len(checked)} requests: "
                 f"{serving['oracle_worst_rel_l2_bf16']:.2e}")
-        log(f"[bench] oracle parity checks of batches and serving took {time.perf_counter() - t1:.1f} s")
+        if anchor_out is not None:
+            from oracle.simulate import simulate_pixels as osimulate_pixels
+            rng = np.random.default_rng(7)
+            pix = [(0, y, x) for y in (0, H // 2, H - 1) for x in (0, W // 2, W - 1)]
+            pix += [(0, int(y), int(x)) for y, x in zip(rng.integers(0, H, 247), rng.integers(0, W, 247))]
+            ref = osimulate_pixels(img_h, fr.d_over_r0, basis, Ws, bs, fr.field_seed, pix, n_zernike=NZ,
+                                   field_model="anchor", G=ANCHOR_GRID, anchor_corr=ANCHOR_CORR)
+            idx = tuple(np.array(pix).T)
+            anchor["rel_l2_bf16_vs_oracle"] = float(np.linalg.norm(anchor_out[idx] - ref) / np.linalg.norm(ref))
+            anchor["oracle_compared_on"] = f"{len(pix)} sampled pixels"
+            log(f"[bench] anchor frame: BF16 rel-L2 vs oracle {anchor['rel_l2_bf16_vs_oracle']:.2e}")
+        log(f"[bench] oracle parity checks of batches, serving and anchor frames took {time.perf_counter() - t1:.1f} s")
         log(f"[bench] oracle {cpu['value']:.3f} frames/s; rel-L2 vs oracle: " +
             ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
 
@@ -744,6 +835,7 @@ def main():
                 "note": "blur on FP8 E4M3 MFMA with per-basis power-of-two scales; network in BF16"},
         "stages_us": {p: res[p]["stages_us"] for p in res},
         "roofline": roofline,
+        "anchor_fields": anchor,
         "batches": batches,
         "serving": serving,
         "cpu_baseline": cpu,
