@@ -188,6 +188,52 @@ def anchor_section(args, torch, p2s, sim, img, fr, NZ, H, W, C, stream):
     return res, kept
 
 
+def spectral_section(args, torch, p2s, S, ptrain):
+    """spectral512: 512 x 512 RGB frames with one wavelength per channel (450,
+    540, 570 nm), each through its own basis and trained network (three fused
+    network-and-blur launches per frame), fields and warp shared.  BF16 and
+    FP32 throughput; one BF16 output kept for the oracle."""
+    from paper_2107_11627_amd import spectral
+    wl = S.workload("spectral512")
+    fr = wl.frames[0]
+    z, d = wl.basis_draws()
+    t0 = time.perf_counter()
+    bases, Ws, bs = [], [], []
+    for lam in wl.extra["wavelengths_nm"]:
+        B = ptrain.workload_basis(wl, lam)
+        w, b, _ = ptrain.load(f"p2s_rgb{int(lam)}", B)
+        bases.append(B)
+        Ws.append(w)
+        bs.append(b)
+    setup_s = time.perf_counter() - t0
+    sim = spectral.SpectralSimulator(bases, Ws, bs, n_zernike=wl.n_zernike)
+    img_h = fr.image()
+    img = torch.from_numpy(img_h).cuda()
+    out = torch.empty_like(img)
+    stream = torch.cuda.current_stream()
+    res = {"workload": "spectral512: 512x512 RGB, D/r0=3, channels at 450/540/570 nm, one K=100 basis of 33x33 "
+                       "and one trained network 33-100-100-100 per channel", "host_setup_s": setup_s}
+    for prec in ("bf16", "fp32"):
+        for i in range(args.warmup):
+            sim(img, fr.d_over_r0, 1000 + i, prec, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(args.steps):
+            sim(img, fr.d_over_r0, 4000 + i, prec, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        res[prec] = {"frames_per_s": 1e3 / ms, "ms_per_frame": ms}
+    sim(img, fr.d_over_r0, fr.field_seed, "bf16", out=out)
+    torch.cuda.synchronize()
+    kept = {"image": img_h, "out": out.cpu().numpy().astype(np.float64), "bases": bases, "Ws": Ws, "bs": bs,
+            "d": fr.d_over_r0, "seed": fr.field_seed}
+    log(f"[bench] spectral512: BF16 {res['bf16']['frames_per_s']:.0f} frames/s, FP32 "
+        f"{res['fp32']['frames_per_s']:.0f} frames/s")
+    return res, kept
+
+
 def mlp_blur_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C, dims):
     """Only the kernel the frame spends most time in (network inside the
     blur), args.steps launches on one frame's fields."""
@@ -578,6 +624,7 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=2)
     ap.add_argument("--serving-max-batch", type=int, default=16)
     ap.add_argument("--no-anchors", action="store_true")
+    ap.add_argument("--no-spectral", action="store_true")
     ap.add_argument("--mode", choices=["frame", "blur", "mlp", "mlp_blur", "pipeline", "fields", "anchor_fields",
                                        "warp", "copy"],
                     default="frame",
@@ -746,6 +793,7 @@ def main():
 
     anchor, anchor_out = (None, None) if args.no_anchors else anchor_section(args, torch, p2s, sim, img, fr, NZ, H,
                                                                               W, C, stream)
+    spec, spec_out = (None, None) if args.no_spectral else spectral_section(args, torch, p2s, S, ptrain)
     batches, batch_samples = (None, {}) if args.no_batches else batch_section(args, torch, p2s, S, pbasis, ptrain)
     serving, serving_samples = (None, None) if args.no_serving else serving_section(args, torch, p2s, S, pbasis, ptrain)
 
@@ -806,7 +854,20 @@ def main():
             anchor["rel_l2_bf16_vs_oracle"] = float(np.linalg.norm(anchor_out[idx] - ref) / np.linalg.norm(ref))
             anchor["oracle_compared_on"] = f"{len(pix)} sampled pixels"
             log(f"[bench] anchor frame: BF16 rel-L2 vs oracle {anchor['rel_l2_bf16_vs_oracle']:.2e}")
-        log(f"[bench] oracle parity checks of batches, serving and anchor frames took {time.perf_counter() - t1:.1f} s")
+        if spec_out is not None:
+            from oracle import spectral as ospec
+            rng = np.random.default_rng(8)
+            pix = [(c, y, x) for c in range(3) for y in (0, 255, 511) for x in (0, 256, 511)]
+            pix += [(int(c), int(y), int(x)) for c, y, x in zip(rng.integers(0, 3, 223), rng.integers(0, 512, 223),
+                                                                 rng.integers(0, 512, 223))]
+            ref = ospec.simulate_spectral_pixels(spec_out["image"], spec_out["d"], spec_out["bases"], spec_out["Ws"],
+                                                 spec_out["bs"], spec_out["seed"], pix)
+            idx = tuple(np.array(pix).T)
+            spec["rel_l2_bf16_vs_oracle"] = float(np.linalg.norm(spec_out["out"][idx] - ref) / np.linalg.norm(ref))
+            spec["oracle_compared_on"] = f"{len(pix)} sampled pixels"
+            log(f"[bench] spectral frame: BF16 rel-L2 vs oracle {spec['rel_l2_bf16_vs_oracle']:.2e}")
+        log(f"[bench] oracle parity checks of batches, serving, anchor and spectral frames took "
+            f"{time.perf_counter() - t1:.1f} s")
         log(f"[bench] oracle {cpu['value']:.3f} frames/s; rel-L2 vs oracle: " +
             ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
 
@@ -836,6 +897,7 @@ def main():
         "stages_us": {p: res[p]["stages_us"] for p in res},
         "roofline": roofline,
         "anchor_fields": anchor,
+        "spectral": spec,
         "batches": batches,
         "serving": serving,
         "cpu_baseline": cpu,

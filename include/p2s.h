@@ -223,6 +223,22 @@ int p2s_simulate_noalloc(const float* image, int C, int H, int W, double D_over_
                          p2s_basis_t basis, p2s_mlp_t mlp, uint64_t seed, p2s_precision precision,
                          const p2s_params* params, float* out, void* stream);
 
+/* Wavelength-dependent colour (Sec. 3.5): channel c of a C-channel frame is
+ * blurred with the PSFs of its own wavelength, through bases[c] and mlps[c]
+ * (host arrays of C handles, read during the call), instead of one basis
+ * and network for every channel.  The fields (stage 1) are shared: they are
+ * the coefficients at a reference wavelength, and each channel's network
+ * maps those to its own basis' weights (the wavelength's phase scale and
+ * sampling live in its training and basis).  The tilt displacement is the
+ * same at every wavelength, so every channel is warped by planes 0 and 1.
+ * Otherwise as p2s_simulate: channel c computes exactly what p2s_simulate
+ * computes for a one-channel frame of plane c with bases[c] and mlps[c].
+ * ws: at least p2s_workspace_bytes(C, H, W, n_zernike, K, params) with K the
+ * largest basis size among the channels. */
+int p2s_simulate_spectral(const float* image, int C, int H, int W, double D_over_r0, int n_zernike,
+                          const p2s_basis_t* bases, const p2s_mlp_t* mlps, uint64_t seed, p2s_precision precision,
+                          const p2s_params* params, float* out, void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------- anchor grid --
  * The paper's own field model (Sec. 3.4, "Interpolation across the grid",
  * with the mode covariance R_Z of Sec. 2.2): the Zernike coefficients of a

@@ -22,15 +22,16 @@ from .psf import psf_from_zernike
 
 
 def dataset(normals: np.ndarray, d_over_r0: np.ndarray, modes=range(4, 37),
-            Np: int = 32, Q: int = 2, P: int = 33, chunk: int = 1024) -> np.ndarray:
-    """PSFs [n][P][P] for alpha_j = normals[:, i] * sqrt(V_j (D/r0)^(5/3))."""
+            Np: int = 32, Q: float = 2, P: int = 33, chunk: int = 1024, phase_scale: float = 1.0) -> np.ndarray:
+    """PSFs [n][P][P] for alpha_j = normals[:, i] * sqrt(V_j (D/r0)^(5/3)),
+    sampled at Q pixels per lambda/D, phase scaled by phase_scale."""
     modes = list(modes)
     var = np.array([noll_variance(j) for j in modes])
     sig = np.sqrt(var[None, :] * np.asarray(d_over_r0, dtype=np.float64)[:, None] ** (5.0 / 3.0))
     alpha = np.asarray(normals, dtype=np.float64) * sig
     out = []
     for s in range(0, alpha.shape[0], chunk):
-        out.append(psf_from_zernike(alpha[s:s + chunk], modes, Np, Q, P))
+        out.append(psf_from_zernike(alpha[s:s + chunk], modes, Np, Q, P, phase_scale))
     return np.concatenate(out, axis=0)
 
 

@@ -50,9 +50,33 @@ def psf_from_phase(phase: np.ndarray, mask: np.ndarray, Q: int, P: int, normalis
     return h
 
 
-def psf_from_zernike(alpha: np.ndarray, modes, Np: int = 32, Q: int = 2, P: int = 33) -> np.ndarray:
-    """PSFs for Zernike coefficient vectors alpha [..., len(modes)]."""
+def psf_from_phase_q(phase: np.ndarray, mask: np.ndarray, q: float, P: int, normalise: bool = True) -> np.ndarray:
+    """Eq. 2 sampled at q pixels per lambda/D for any real q > 0: the field
+    at pixel offset (v, u), |u|, |v| <= R, is the discrete Fourier sum
+    sum_{y,x} W e^{-j phi} exp(-2 pi i (u x + v y) / (q Np)) over the pupil
+    samples (for integer q these are the bins of the zero-padded FFT)."""
+    Np = mask.shape[-1]
+    R = (P - 1) // 2
+    u = np.arange(-R, R + 1, dtype=np.float64)
+    x = np.arange(Np, dtype=np.float64)
+    A = np.exp(-2j * np.pi * np.outer(u, x) / (q * Np))          # [P][Np]
+    field = mask * np.exp(-1j * phase)
+    E = A @ field @ A.T                                           # rows v, columns u
+    h = np.abs(E) ** 2
+    if normalise:
+        h = h / h.sum(axis=(-2, -1), keepdims=True)
+    return h
+
+
+def psf_from_zernike(alpha: np.ndarray, modes, Np: int = 32, Q: float = 2, P: int = 33,
+                     phase_scale: float = 1.0) -> np.ndarray:
+    """PSFs for Zernike coefficient vectors alpha [..., len(modes)]; the phase
+    is phase_scale * sum alpha_j Z_j (a wavelength other than the one alpha
+    is given at: phase_scale = lambda_ref / lambda); non-integer sampling Q
+    goes through psf_from_phase_q."""
     Z = zernike_stack(modes, Np)
     _, _, mask = pupil_grid(Np)
-    phase = np.tensordot(np.asarray(alpha, dtype=np.float64), Z, axes=([-1], [0]))
-    return psf_from_phase(phase, mask, Q, P)
+    phase = phase_scale * np.tensordot(np.asarray(alpha, dtype=np.float64), Z, axes=([-1], [0]))
+    if float(Q) == int(Q):
+        return psf_from_phase(phase, mask, int(Q), P)
+    return psf_from_phase_q(phase, mask, float(Q), P)

@@ -3,7 +3,7 @@
 This module holds no arithmetic of the simulation method itself: it only draws
 random inputs (images, network weights, the standard normals behind the PSF
 dataset, per-frame D/r0 and sizes) from NumPy's PCG64 generator and describes
-the five workloads by their sizes and seeds.  Both sides receive exactly the
+the six workloads by their sizes and seeds.  Both sides receive exactly the
 same arrays from here; neither side's arithmetic lives here.
 
 Workloads (sizes follow the paper's 256x256 timing frame and its M=100 basis,
@@ -17,6 +17,9 @@ in the design notes):
 * ``serving``    1000 requests, sizes 128..2048 (multiples of 64), RGB,
                  admission budget 32 GiB; Poisson arrivals at 70 % of the
                  saturated request rate measured in the same run.
+* ``spectral512`` 512x512 RGB, D/r0=3, one K=100 basis of 33x33 and one
+                 MLP 33-100-100-100 per channel, channels at 450, 540 and
+                 570 nm (reference wavelength 525 nm).
 """
 from __future__ import annotations
 
@@ -202,6 +205,11 @@ def workload(name: str) -> Workload:
         return Workload(name, [FrameSpec(512, 512, 1, 3.0, 10, 11)], K=100, P=33, n_psf=8192,
                         basis_seed=13, basis_d_over_r0=(3.0, 3.0), mlp_dims=(33, 100, 100, 100),
                         model_seed=12, extra={"latency_field_seeds": list(range(100, 300))})
+    if name == "spectral512":
+        # RGB frame with one PSF wavelength per channel (blue, green, red)
+        return Workload(name, [FrameSpec(512, 512, 3, 3.0, 16, 17)], K=100, P=33, n_psf=8192,
+                        basis_seed=15, basis_d_over_r0=(3.0, 3.0), mlp_dims=(33, 100, 100, 100),
+                        model_seed=12, extra={"wavelengths_nm": (450.0, 540.0, 570.0), "reference_nm": 525.0})
     shared = dict(K=100, P=33, n_psf=8192, basis_seed=14, basis_d_over_r0=(0.5, 6.0),
                   mlp_dims=(33, 100, 100, 100), model_seed=12)
     if name == "batch256":
@@ -230,4 +238,4 @@ def workload(name: str) -> Workload:
     raise KeyError(name)
 
 
-WORKLOADS = ("single128", "single512", "batch256", "ragged", "serving")
+WORKLOADS = ("single128", "single512", "batch256", "ragged", "serving", "spectral512")

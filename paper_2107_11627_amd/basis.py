@@ -46,24 +46,36 @@ def zernike_on_pupil(j: int, Np: int) -> np.ndarray:
 
 
 def psf_dataset(normals: np.ndarray, d_over_r0: np.ndarray, P: int, n_zernike: int = 35,
-                Np: int = 32, Q: int = 2, chunk: int = 512) -> np.ndarray:
+                Np: int = 32, Q: float = 2, chunk: int = 512, phase_scale: float = 1.0) -> np.ndarray:
+    """PSFs [n][P][P] of alpha_4.. = normals * sqrt(V_j (D/r0)^(5/3)), the phase
+    multiplied by phase_scale (lambda_ref / lambda for another wavelength),
+    sampled at Q pixels per lambda/D: by a zero-padded FFT for integer Q,
+    else by the Fourier sum at the P x P output offsets directly."""
     modes = np.arange(4, n_zernike + 2)
     sig = np.sqrt(np.array([p2s.noll_variance(int(j)) for j in modes]))
     Zs = np.stack([zernike_on_pupil(int(j), Np) for j in modes]).reshape(len(modes), -1)
     c = (np.arange(Np) + 0.5) * (2.0 / Np) - 1.0
     pupil = (c[None, :] ** 2 + c[:, None] ** 2 <= 1.0).astype(np.float64)
-    nf = Q * Np
     R = (P - 1) // 2
+    integer_q = float(Q) == int(Q)
+    if integer_q:
+        nf = int(Q) * Np
+    else:
+        # F[u][x] = exp(-2 pi i u x / (Q Np)), u = -R..R output offsets
+        F = np.exp(-2j * np.pi * np.outer(np.arange(-R, R + 1), np.arange(Np)) / (float(Q) * Np))
     out = np.empty((normals.shape[0], P, P))
     d53 = np.asarray(d_over_r0, dtype=np.float64) ** (5.0 / 6.0)   # sqrt of (D/r0)^(5/3)
     for s0 in range(0, normals.shape[0], chunk):
         a = normals[s0:s0 + chunk] * sig[None, :] * d53[s0:s0 + chunk, None]
-        phase = (a @ Zs).reshape(-1, Np, Np)
-        field = np.zeros((phase.shape[0], nf, nf), dtype=np.complex128)
-        field[:, :Np, :Np] = pupil * np.exp(-1j * phase)
-        spec = np.fft.fft2(field)
-        h = np.roll(np.abs(spec) ** 2, (nf // 2, nf // 2), axis=(1, 2))[:, nf // 2 - R:nf // 2 + R + 1,
-                                                                         nf // 2 - R:nf // 2 + R + 1]
+        phase = phase_scale * (a @ Zs).reshape(-1, Np, Np)
+        if integer_q:
+            field = np.zeros((phase.shape[0], nf, nf), dtype=np.complex128)
+            field[:, :Np, :Np] = pupil * np.exp(-1j * phase)
+            spec = np.fft.fft2(field)
+            h = np.roll(np.abs(spec) ** 2, (nf // 2, nf // 2), axis=(1, 2))[:, nf // 2 - R:nf // 2 + R + 1,
+                                                                             nf // 2 - R:nf // 2 + R + 1]
+        else:
+            h = np.abs(F @ (pupil * np.exp(-1j * phase)) @ F.T) ** 2
         out[s0:s0 + chunk] = h / h.sum(axis=(1, 2), keepdims=True)
     return out
 
@@ -85,5 +97,6 @@ def pca(psfs: np.ndarray, K: int):
     return B.reshape(K, P, P), sv[:K] ** 2
 
 
-def learn_basis(normals: np.ndarray, d_over_r0: np.ndarray, K: int, P: int, n_zernike: int = 35):
-    return pca(psf_dataset(normals, d_over_r0, P, n_zernike), K)
+def learn_basis(normals: np.ndarray, d_over_r0: np.ndarray, K: int, P: int, n_zernike: int = 35,
+                Q: float = 2, phase_scale: float = 1.0):
+    return pca(psf_dataset(normals, d_over_r0, P, n_zernike, Q=Q, phase_scale=phase_scale), K)

@@ -857,6 +857,80 @@ int simulate_impl(const float* image, int C, int H, int W, double D_over_r0, int
 }  // namespace
 }  // namespace p2s
 
+namespace p2s {
+namespace {
+
+// One colour frame with a basis and a network per channel: shared fields,
+// channel c through its own network and blur (fused where that form applies),
+// then every channel warped by the shared tilt.
+int spectral_impl(const float* image, int C, int H, int W, double D_over_r0, int n_zernike, const p2s_basis_t* bases,
+                  const p2s_mlp_t* mlps, uint64_t seed, p2s_precision precision, const p2s_params* params,
+                  float* out, void* ws, size_t ws_bytes, hipStream_t s) {
+    Params pr;
+    int rc = read_params(params, &pr);
+    if (rc) return rc;
+    rc = check_frame(C, H, W);
+    if (rc) return rc;
+    rc = check_prec(precision);
+    if (rc) return rc;
+    if (!bases || !mlps) return fail(P2S_EINVAL, "bases or mlps is NULL");
+    if (n_zernike < 3 || n_zernike > P2S_MAX_ZERNIKE)
+        return fail(P2S_EINVAL, "n_zernike must be in [3, %d], got %d", P2S_MAX_ZERNIKE, n_zernike);
+    int Kmax = 0;
+    bool fused[P2S_MAX_CHANNELS];
+    for (int c = 0; c < C; ++c) {
+        if (!bases[c] || !mlps[c]) return fail(P2S_EINVAL, "basis or mlp of channel %d is NULL", c);
+        const Mlp& m = mlps[c]->m;
+        const Basis& b = bases[c]->b;
+        if (m.dims[0] != n_zernike - 2)
+            return fail(P2S_EINVAL, "channel %d: n_zernike - 2 = %d does not match the network input width %d", c,
+                        n_zernike - 2, m.dims[0]);
+        if (m.dims[m.L] != b.K)
+            return fail(P2S_EINVAL, "channel %d: network output width %d does not match the basis size K = %d", c,
+                        m.dims[m.L], b.K);
+        if (precision != P2S_FP32 && !b.bf16_ok)
+            return fail(P2S_EUNSUPPORTED, "channel %d: BF16 and FP8 blur need a PSF side P = 8a + 1; got %d", c, b.P);
+        Kmax = std::max(Kmax, b.K);
+        fused[c] = blur_mlp_supported(b, m, precision);
+    }
+    if (!image || !out || !ws) return fail(P2S_EINVAL, "image, out or workspace is NULL");
+    if (!(std::isfinite(D_over_r0) && D_over_r0 >= 0.0)) return fail(P2S_EINVAL, "D/r0 must be finite and >= 0");
+    const int Nfy = grid_of(H, pr.corr_len), Nfx = grid_of(W, pr.corr_len);
+    if (Nfy > kMaxFftLen || Nfx > kMaxFftLen)
+        return fail(P2S_EUNSUPPORTED, "noise grid %d x %d exceeds the single-workgroup FFT limit %d", Nfy, Nfx, kMaxFftLen);
+    const SimLayout L = sim_layout(C, H, W, n_zernike, Kmax, pr, true);
+    if (ws_bytes < L.total) return fail(P2S_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    const size_t HW = (size_t)H * W, n = (size_t)C * HW * 4;
+    if (overlap(image, n, out, n)) return fail(P2S_EINVAL, "image and out overlap");
+    if (overlap(ws, L.total, out, n) || overlap(ws, L.total, image, n))
+        return fail(P2S_EINVAL, "workspace overlaps image or out");
+    char* base = (char*)ws;
+    float* F = (float*)(base + L.fields);
+    float* r2 = (float*)(base + L.region2);
+    float* bl = (float*)(base + L.blurred);
+    rc = make_fields_impl(H, W, D_over_r0, n_zernike, seed, pr, F, r2, L.blurred - L.region2, s);
+    if (rc) return rc;
+    for (int c = 0; c < C; ++c) {
+        const float* img_c = image + c * HW;
+        float* bl_c = bl + c * HW;
+        if (fused[c]) {
+            hipError_t e = launch_blur_mlp(bases[c]->b, mlps[c]->m, precision, img_c, 1, H, W, F, bl_c, s);
+            if (e != hipSuccess) return hip_fail(e, "fused network and blur kernel");
+        } else {
+            rc = mlp_impl(mlps[c]->m, F, n_zernike, H, W, precision, r2, s);
+            if (rc) return rc;
+            rc = blur_impl(img_c, 1, H, W, bases[c]->b, r2, precision, bl_c, s);
+            if (rc) return rc;
+        }
+    }
+    rc = warp_impl(bl, C, H, W, F, pr, out, s);
+    if (rc) return rc;
+    return ok();
+}
+
+}  // namespace
+}  // namespace p2s
+
 struct p2s_batch_s {
     p2s::BatchHost* h;
 };
@@ -1132,6 +1206,13 @@ int p2s_simulate_anchor(const float* image, int C, int H, int W, double D_over_r
     if (!anchors) return fail(P2S_EINVAL, "anchors is NULL");
     return simulate_impl(image, C, H, W, D_over_r0, anchors->a.n, basis, mlp, seed, precision, params, out, ws,
                          ws_bytes, false, (hipStream_t)stream, &anchors->a);
+}
+
+int p2s_simulate_spectral(const float* image, int C, int H, int W, double D_over_r0, int n_zernike,
+                          const p2s_basis_t* bases, const p2s_mlp_t* mlps, uint64_t seed, p2s_precision precision,
+                          const p2s_params* params, float* out, void* ws, size_t ws_bytes, void* stream) {
+    return spectral_impl(image, C, H, W, D_over_r0, n_zernike, bases, mlps, seed, precision, params, out, ws,
+                         ws_bytes, (hipStream_t)stream);
 }
 
 size_t p2s_batch_workspace_bytes(const p2s_frame* frames, int n, int n_zernike, int K, const p2s_params* params) {

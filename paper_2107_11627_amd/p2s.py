@@ -30,7 +30,7 @@ EXPORTS = [
     "p2s_batch_upload", "p2s_batch_launch", "p2s_batch_info", "p2s_batch_destroy", "p2s_simulate_batch",
     "p2s_simulate_noalloc", "p2s_anchor_create", "p2s_anchor_destroy", "p2s_anchor_info",
     "p2s_anchor_fields_workspace_bytes", "p2s_make_fields_anchor", "p2s_workspace_bytes_anchor",
-    "p2s_simulate_anchor",
+    "p2s_simulate_anchor", "p2s_simulate_spectral",
 ]
 
 
@@ -107,6 +107,7 @@ def lib():
         L.p2s_workspace_bytes_anchor.argtypes = [vp, i, i, i, i]
         L.p2s_workspace_bytes_anchor.restype = sz
         L.p2s_simulate_anchor.argtypes = [vp, i, i, i, d, vp, vp, vp, u64, i, vp, vp, vp, sz, vp]
+        L.p2s_simulate_spectral.argtypes = [vp, i, i, i, d, i, vp, vp, u64, i, vp, vp, vp, sz, vp]
         sized = ("p2s_version", "p2s_last_error", "p2s_fields_workspace_bytes", "p2s_workspace_bytes",
                  "p2s_batch_workspace_bytes", "p2s_anchor_fields_workspace_bytes", "p2s_workspace_bytes_anchor")
         for name in EXPORTS:
@@ -339,6 +340,21 @@ def simulate(image, d_over_r0, basis: Basis, net: Mlp, seed, precision, out, ws,
                               basis.handle, net.handle, int(seed) & (2 ** 64 - 1), _prec(precision),
                               _params(corr_len_px, q_sampling), _ptr(out, torch.float32, (C_, H, W), "out"),
                               _ptr(ws, name="ws"), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def simulate_spectral(image, d_over_r0, bases: Sequence[Basis], nets: Sequence[Mlp], seed, precision, out, ws,
+                      n_zernike=35, corr_len_px=16.0, q_sampling=2.0, stream=None):
+    """One colour frame with a basis and a network per channel."""
+    import torch
+    C_, H, W = image.shape
+    if len(bases) != C_ or len(nets) != C_:
+        raise ValueError(f"need {C_} bases and {C_} networks, got {len(bases)} and {len(nets)}")
+    cb = (C.c_void_p * C_)(*[b.handle for b in bases])
+    cn = (C.c_void_p * C_)(*[n.handle for n in nets])
+    _check(lib().p2s_simulate_spectral(_ptr(image, torch.float32, None, "image"), C_, H, W, float(d_over_r0),
+                                       n_zernike, cb, cn, int(seed) & (2 ** 64 - 1), _prec(precision),
+                                       _params(corr_len_px, q_sampling), _ptr(out, torch.float32, (C_, H, W), "out"),
+                                       _ptr(ws, name="ws"), ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def simulate_noalloc(image, d_over_r0, basis: Basis, net: Mlp, seed, precision, out, n_zernike=35,

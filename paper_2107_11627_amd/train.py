@@ -41,13 +41,16 @@ def zernike_sigmas(n_zernike: int = 35) -> np.ndarray:
     return np.sqrt(np.array([p2s.noll_variance(int(j)) for j in range(4, n_zernike + 2)]))
 
 
-def training_pairs(normals: np.ndarray, d_over_r0: np.ndarray, basis: np.ndarray, n_zernike: int = 35):
+def training_pairs(normals: np.ndarray, d_over_r0: np.ndarray, basis: np.ndarray, n_zernike: int = 35,
+                   Q: float = 2, phase_scale: float = 1.0):
     """(alpha [n][n_zernike-2], beta [n][K]) for standard normals and D/r0
     draws: alpha_j = normal * sqrt(V_j (D/r0)^(5/3)); beta = projection of
-    the Eq. 2 PSF of alpha onto the basis."""
+    the Eq. 2 PSF of alpha onto the basis (for another wavelength: the PSF of
+    phase_scale alpha sampled at Q pixels per lambda/D, while the network's
+    input stays the reference alpha)."""
     K, P, _ = basis.shape
     alpha = normals * zernike_sigmas(n_zernike)[None, :] * (np.asarray(d_over_r0) ** (5.0 / 6.0))[:, None]
-    psfs = pbasis.psf_dataset(normals, d_over_r0, P, n_zernike)
+    psfs = pbasis.psf_dataset(normals, d_over_r0, P, n_zernike, Q=Q, phase_scale=phase_scale)
     beta = psfs.reshape(len(psfs), P * P) @ basis.reshape(K, P * P).T
     return alpha, beta
 
@@ -170,31 +173,51 @@ def load(name: str, basis: np.ndarray = None):
     return Ws, bs, meta
 
 
-# Models of the synthetic workloads: (name, workload whose basis it serves,
-# training D/r0 range, training seed).  The single-frame workload's basis is
-# learned at D/r0 = 3, the shared one over [0.5, 6].
+# Models of the synthetic workloads: (workload whose basis it serves,
+# training D/r0 range, training seed, PSF wavelength in nm or None for the
+# reference wavelength).  The single-frame workload's basis is learned at
+# D/r0 = 3, the shared one over [0.5, 6]; the spectral workload has one basis
+# and one network per channel wavelength.
 MODELS = {
-    "p2s_single512": ("single512", (2.0, 4.0), 201),
-    "p2s_shared": ("batch256", (0.5, 6.0), 202),
+    "p2s_single512": ("single512", (2.0, 4.0), 201, None),
+    "p2s_shared": ("batch256", (0.5, 6.0), 202, None),
+    "p2s_rgb450": ("spectral512", (2.0, 4.0), 211, 450.0),
+    "p2s_rgb540": ("spectral512", (2.0, 4.0), 212, 540.0),
+    "p2s_rgb570": ("spectral512", (2.0, 4.0), 213, 570.0),
 }
+
+
+def workload_basis(wl, wavelength_nm=None):
+    """The PCA basis a model of workload wl serves (at a channel wavelength
+    for the spectral workload)."""
+    z, d = wl.basis_draws()
+    if wavelength_nm is None:
+        return pbasis.learn_basis(z, d, wl.K, wl.P, wl.n_zernike)[0]
+    from . import spectral
+    return spectral.channel_basis(z, d, wl.K, wl.P, wavelength_nm, wl.n_zernike)[0]
 
 
 def build_model(name: str, n_train: int = 65536, n_test: int = 4096, steps: int = 20000, log=print):
     """Train and store the named model; returns (path, held-out relative
     l2 error of beta)."""
     import p2s_synth as S
-    wl_name, (dlo, dhi), seed = MODELS[name]
+    wl_name, (dlo, dhi), seed, lam = MODELS[name]
     wl = S.workload(wl_name)
-    z, d = wl.basis_draws()
-    B, _ = pbasis.learn_basis(z, d, wl.K, wl.P, wl.n_zernike)
+    B = workload_basis(wl, lam)
     rng = np.random.default_rng(seed)
     nz = rng.standard_normal((n_train + n_test, wl.n_zernike - 2))
     dd = rng.uniform(dlo, dhi, n_train + n_test)
-    alpha, beta = training_pairs(nz, dd, B, wl.n_zernike)
+    if lam is None:
+        alpha, beta = training_pairs(nz, dd, B, wl.n_zernike)
+    else:
+        from . import spectral
+        q, s = spectral.channel_sampling(lam)
+        alpha, beta = training_pairs(nz, dd, B, wl.n_zernike, Q=q, phase_scale=s)
     Ws, bs = train(alpha[:n_train], beta[:n_train], wl.mlp_dims, seed, steps=steps, log=log)
     pred = forward(Ws, bs, alpha[n_train:])
     err = float(np.linalg.norm(pred - beta[n_train:]) / np.linalg.norm(beta[n_train:]))
     meta = {"workload_basis": wl_name, "basis_fingerprint": basis_fingerprint(B), "dims": list(wl.mlp_dims),
+            "wavelength_nm": lam,
             "train": {"n": n_train, "seed": seed, "d_over_r0": [dlo, dhi], "steps": steps, "batch": 1024,
                       "lr": 2e-3, "schedule": "cosine", "optimizer": "Adam", "loss": "mean squared l2 of beta"},
             "held_out": {"n": n_test, "rel_l2_beta": err}}

@@ -196,3 +196,32 @@ def test_product_anchor_setup_matches_oracle():
         assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
     for G, l in ((2, 1.0), (7, 2.0), (12, 3.5)):
         assert np.max(np.abs(panch.anchor_correlation(G, l) - oanch.anchor_correlation(G, l))) < 1e-15
+
+
+def test_product_psf_dataset_any_wavelength_matches_oracle():
+    """The package's PSF dataset at a non-integer sampling and a scaled phase
+    (another wavelength than the reference) equals the oracle's: the
+    package's direct Fourier sum against the oracle's psf_from_phase_q."""
+    from paper_2107_11627_amd import basis as pb
+    z = np.random.default_rng(8).standard_normal((40, 33))
+    d = np.random.default_rng(9).uniform(1.0, 4.0, 40)
+    for q, s in ((2.0 * 450 / 525, 525 / 450), (2.0 * 570 / 525, 525 / 570)):
+        a = pb.psf_dataset(z, d, 17, 35, Q=q, phase_scale=s)
+        b = obasis.dataset(z, d, P=17, Q=q, phase_scale=s)
+        assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_spectral_validation_without_device(p2s):
+    """p2s_simulate_spectral rejects NULL handle arrays, a bad channel count and
+    a bad mode count before touching a device."""
+    lib = p2s.lib()
+    assert lib.p2s_simulate_spectral(None, 3, 8, 8, 1.0, 35, None, None, 0, 1, None, None, None, 0,
+                                     None) == p2s.P2S_EINVAL
+    assert lib.p2s_simulate_spectral(None, 0, 8, 8, 1.0, 35, None, None, 0, 1, None, None, None, 0,
+                                     None) == p2s.P2S_EINVAL
+    nulls = (C.c_void_p * 3)(None, None, None)
+    assert lib.p2s_simulate_spectral(None, 3, 8, 8, 1.0, 35, nulls, nulls, 0, 1, None, None, None, 0,
+                                     None) == p2s.P2S_EINVAL
+    assert b"channel 0" in lib.p2s_last_error()
+    assert lib.p2s_simulate_spectral(None, 3, 8, 8, 1.0, 2, nulls, nulls, 0, 1, None, None, None, 0,
+                                     None) == p2s.P2S_EINVAL

@@ -2,7 +2,8 @@
 
 The models under paper_2107_11627_amd/weights were trained by the package's
 host trainer on PSFs it formed itself; here the oracle forms independent
-held-out PSFs with its own Eq. 2 and PCA-free projection, and checks:
+held-out PSFs with its own Eq. 2 (at the model's wavelength for the per-channel
+colour models) and PCA-free projection, and checks:
   * the network's basis coefficients on held-out Zernike draws against the
     projections of the oracle's PSFs (relative l2 of beta);
   * zero turbulence: the network at alpha = 0 against the projection of the
@@ -18,31 +19,32 @@ import p2s_synth as S
 from oracle import basis as obasis
 from oracle import mlp as omlp
 from oracle import psf as opsf
+from oracle import spectral
 from oracle.simulate import simulate
 
 
 @pytest.fixture(scope="module")
 def models():
-    from paper_2107_11627_amd import basis as pb
     from paper_2107_11627_amd import train
     out = {}
-    for name, (wl_name, drange, _) in train.MODELS.items():
+    for name, (wl_name, drange, _, lam) in train.MODELS.items():
         wl = S.workload(wl_name)
-        z, d = wl.basis_draws()
-        B, _ = pb.learn_basis(z, d, wl.K, wl.P, wl.n_zernike)
+        B = train.workload_basis(wl, lam)
         Ws, bs, meta = train.load(name, B)           # checks the content hash and the basis
-        out[name] = (B, Ws, bs, meta, drange, wl)
+        q, s = spectral.channel_sampling(lam) if lam else (2.0, 1.0)
+        out[name] = (B, Ws, bs, meta, drange, wl, q, s)
     return out
 
 
-@pytest.mark.parametrize("name,bound", [("p2s_single512", 0.12), ("p2s_shared", 0.15)])
+@pytest.mark.parametrize("name,bound", [("p2s_single512", 0.12), ("p2s_shared", 0.15), ("p2s_rgb450", 0.15),
+                                        ("p2s_rgb540", 0.12), ("p2s_rgb570", 0.12)])
 def test_held_out_coefficients(models, name, bound):
-    B, Ws, bs, meta, (dlo, dhi), wl = models[name]
+    B, Ws, bs, meta, (dlo, dhi), wl, q, s = models[name]
     rng = np.random.default_rng(987)
     n = 1024
     z = rng.standard_normal((n, wl.n_zernike - 2))
     d = rng.uniform(dlo, dhi, n)
-    psfs = obasis.dataset(z, d, P=wl.P)                            # oracle Eq. 2
+    psfs = obasis.dataset(z, d, P=wl.P, Q=q, phase_scale=s)        # oracle Eq. 2 at the model's wavelength
     beta = psfs.reshape(n, -1) @ B.reshape(wl.K, -1).T              # projection on the basis
     from oracle.noll import noll_variance
     sig = np.sqrt(np.array([noll_variance(j) for j in range(4, wl.n_zernike + 2)]))
@@ -53,10 +55,11 @@ def test_held_out_coefficients(models, name, bound):
     assert err < bound
 
 
-@pytest.mark.parametrize("name,bound", [("p2s_single512", 0.06), ("p2s_shared", 0.04)])
+@pytest.mark.parametrize("name,bound", [("p2s_single512", 0.06), ("p2s_shared", 0.04), ("p2s_rgb450", 0.10),
+                                        ("p2s_rgb540", 0.06), ("p2s_rgb570", 0.06)])
 def test_zero_turbulence_gives_airy_projection(models, name, bound):
-    B, Ws, bs, meta, _, wl = models[name]
-    airy = opsf.psf_from_zernike(np.zeros((1, wl.n_zernike - 2)), range(4, wl.n_zernike + 2), 32, 2, wl.P)[0]
+    B, Ws, bs, meta, _, wl, q, s = models[name]
+    airy = opsf.psf_from_zernike(np.zeros((1, wl.n_zernike - 2)), range(4, wl.n_zernike + 2), 32, q, wl.P)[0]
     beta0 = B.reshape(wl.K, -1) @ airy.reshape(-1)
     pred = omlp.forward(Ws, bs, np.zeros((1, wl.n_zernike - 2)))[0]
     err = float(np.linalg.norm(pred - beta0) / np.linalg.norm(beta0))
@@ -65,7 +68,7 @@ def test_zero_turbulence_gives_airy_projection(models, name, bound):
 
 
 def test_constant_image_nearly_preserved(models):
-    B, Ws, bs, meta, _, wl = models["p2s_single512"]
+    B, Ws, bs, meta, _, wl, _, _ = models["p2s_single512"]
     img = np.full((1, 48, 56), 0.6)
     out = simulate(img, 3.0, B, Ws, bs, seed=5)["out"][0] / 0.6
     dev = np.abs(out - 1.0)
