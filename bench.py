@@ -726,28 +726,27 @@ def main():
         fws = torch.empty(p2s.fields_workspace_bytes(H, W, NZ), dtype=torch.uint8, device="cuda")
         bl = torch.empty_like(img)
         fused = prec != "fp32"
-        stages = {"fields": [], "mlp": [], "blur": [], "mlp_blur": [], "warp": []}
-        for r in range(args.stage_reps + 2):
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-            ev[0].record(stream)
-            p2s.make_fields(H, W, fr.d_over_r0, NZ, 1000 + r, F, fws)
-            ev[1].record(stream)
-            p2s.mlp(sim.net, F, NZ, H, W, prec, wbuf)
-            ev[2].record(stream)
-            p2s.blur(img, sim.basis, wbuf, prec, bl)
-            ev[3].record(stream)
-            if fused:                        # network and blur in one kernel, as the frame runs them
-                p2s.mlp_blur(sim.net, F, NZ, img, sim.basis, prec, bl)
-            ev[4].record(stream)
-            p2s.warp(bl, F, out)
-            ev[5].record(stream)
+        # each stage call back to back (args.stage_reps calls between two events,
+        # after two untimed ones), so that every call runs at the clock a busy
+        # device holds, as inside a stream of frames
+        def stage_time(fn):
+            for i in range(2):
+                fn(i)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for i in range(args.stage_reps):
+                fn(2 + i)
+            e1.record(stream)
             torch.cuda.synchronize()
-            if r >= 2:
-                for k, name in enumerate(stages):
-                    stages[name].append(ev[k].elapsed_time(ev[k + 1]) * 1e3)
-        if not fused:
-            del stages["mlp_blur"]
-        res[prec]["stages_us"] = {k: float(np.mean(v)) for k, v in stages.items()}
+            return e0.elapsed_time(e1) * 1e3 / args.stage_reps
+
+        stages = {"fields": stage_time(lambda i: p2s.make_fields(H, W, fr.d_over_r0, NZ, 1000 + i, F, fws)),
+                  "mlp": stage_time(lambda i: p2s.mlp(sim.net, F, NZ, H, W, prec, wbuf)),
+                  "blur": stage_time(lambda i: p2s.blur(img, sim.basis, wbuf, prec, bl))}
+        if fused:                            # network and blur in one kernel, as the frame runs them
+            stages["mlp_blur"] = stage_time(lambda i: p2s.mlp_blur(sim.net, F, NZ, img, sim.basis, prec, bl))
+        stages["warp"] = stage_time(lambda i: p2s.warp(bl, F, out))
+        res[prec]["stages_us"] = stages
         if fused:
             # the dominant kernel's average duration inside the frame pipeline
             ev_us, us, frame_us = pipeline_times(torch, p2s, sim, img, fr, NZ, H, W, prec, args.pipeline_frames,
