@@ -151,12 +151,13 @@ struct WFromNetwork {
     }
 
     // Before the convolutions, while no accumulator is live: the network for
-    // the wave's pixel blocks, two at a time (every weight read from LDS
-    // serves both; more at once would need two full activation sets of
-    // registers for each).
+    // the wave's pixel blocks, two at a time with bf16 hi + lo activations
+    // (every weight read from LDS serves both; more at once would need two
+    // full activation sets of registers for each), four at a time with bf16
+    // activations alone (half the registers per block).
     __device__ __forceinline__ void begin(int, int, int, int) {
         if constexpr (!EVAL) return;
-        constexpr int GB = NBLK >= 2 ? 2 : NBLK;
+        constexpr int GB = !LO && NBLK >= 4 ? 4 : (NBLK >= 2 ? 2 : NBLK);
 #pragma unroll
         for (int b0 = 0; b0 < NBLK; b0 += GB) {
             const float (&ig)[GB][2][8] = *reinterpret_cast<const float (*)[GB][2][8]>(&in[b0]);
@@ -510,7 +511,7 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
 __device__ __forceinline__ uint2 pack_e4m3x8(const float* s, int stride) {
     float v[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = fminf(fmaxf(s[e * stride], -448.0f), 448.0f);
+    for (int e = 0; e < 8; ++e) v[e] = __builtin_amdgcn_fmed3f(s[e * stride], -448.0f, 448.0f);   // clamp, one op
     uint32_t lo = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false) & 0xFFFFu;
     lo |= ((uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], 0, false) & 0xFFFFu) << 16;
     uint32_t hi = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], 0, false) & 0xFFFFu;
