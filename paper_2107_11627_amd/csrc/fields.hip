@@ -558,6 +558,197 @@ __global__ void __launch_bounds__(kThreads) fields_rows_batch(const FrameDesc* _
     }
 }
 
+// ---------------------------------------------------------- fixed plans
+// Transforms whose length N = R0 R1 R2 is known at compile time, with one
+// butterfly per thread and pass: TPF = max(N / R) threads per transform, T
+// transforms per workgroup.  In the runtime-sized passes above a 576-point
+// transform (9 x 8 x 8) on 64 threads runs each radix-8 pass as two rounds,
+// the second with 8 of 64 lanes busy, and forms every index at run time;
+// here every lane of a round has a butterfly (except in the 64-butterfly
+// radix-9 pass) and the index arithmetic folds into constants.  The
+// arithmetic of every butterfly is the runtime path's (same twiddle table
+// entry, same powers by products, same DFT), so both give the same bits.
+//
+// Passes: the sparse first pass (inputs x[j], x[j + N - N/R0]) writes the
+// LDS row of its transform; the middle pass reads its R1 inputs, waits for
+// the whole workgroup, and overwrites them in place; the last pass reads
+// and hands each output to out(f, index, value).
+template <int R0, int R1, int R2, int T>
+struct FixedPlan {
+    static constexpr int N = R0 * R1 * R2;
+    static constexpr int NB0 = N / R0, NB1 = N / R1, NB2 = N / R2;
+    static constexpr int TPF = NB0 > NB1 ? (NB0 > NB2 ? NB0 : NB2) : (NB1 > NB2 ? NB1 : NB2);
+    static constexpr int NT = T * TPF;
+    static constexpr int LD = N | 1;
+    static constexpr size_t lds_bytes = (size_t)(T * LD + N) * 8;
+};
+
+// The first pass's butterfly of this thread: transform t % T, butterfly
+// t / T (consecutive threads take consecutive transforms, so that a
+// column-major source is read in runs of T), valid for t < T N / R0.
+template <int R0, int R1, int R2, int T>
+__device__ __forceinline__ bool fixed_first(int& f, int& j) {
+    using P = FixedPlan<R0, R1, R2, T>;
+    const int t = threadIdx.x;
+    f = t % T;
+    j = t / T;
+    return t < T * P::NB0;
+}
+
+// The transforms of one workgroup; a = x[j], b = x[j + N - N/R0] are the
+// inputs of this thread's first-pass butterfly (fixed_first), the twiddle
+// table tw is in place and a barrier has passed since it was written.
+template <int R0, int R1, int R2, int T, class Out>
+__device__ __forceinline__ void fixed_ifft(float2* __restrict__ buf, const float2* __restrict__ tw, float2 a,
+                                           float2 b, Out&& out) {
+    using P = FixedPlan<R0, R1, R2, T>;
+    constexpr int LD = P::LD;
+    int f1, j1;
+    if (fixed_first<R0, R1, R2, T>(f1, j1)) {    // sparse radix-R0 pass
+        const int f = f1, j = j1;
+        float2 w[R0];
+#pragma unroll
+        for (int k = 0; k < R0; ++k) w[k] = tw[k * P::NB0];
+        float2* row = buf + f * LD + j * R0;
+#pragma unroll
+        for (int k = 0; k < R0; ++k)
+            row[k] = make_float2(a.x + b.x * w[k].x - b.y * w[k].y, a.y + b.x * w[k].y + b.y * w[k].x);
+    }
+    __syncthreads();
+    const int f = threadIdx.x / P::TPF, j = threadIdx.x - f * P::TPF;
+    float2* const row = buf + f * LD;
+    {                                            // radix-R1 pass, in place, Ns = R0
+        constexpr int Ns = R0, step = P::NB1 / Ns;
+        float2 v[R1];
+        const bool act = j < P::NB1;
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < R1; ++r) v[r] = row[j + r * P::NB1];
+        }
+        __syncthreads();                         // every input read before any is overwritten
+        if (act) {
+            const int qj = j / Ns, k = j - qj * Ns;
+            float2 w = tw[k * step];
+            w.y *= -1.0f;
+            float2 wp[R1];
+            twiddle_powers<R1>(w, wp);
+#pragma unroll
+            for (int r = 1; r < R1; ++r) v[r] = cmul(v[r], wp[r]);
+            dft<R1>(v, 1.0f);
+            const int base = qj * Ns * R1 + k;
+#pragma unroll
+            for (int q = 0; q < R1; ++q) row[base + q * Ns] = v[q];
+        }
+    }
+    __syncthreads();
+    if (j < P::NB2) {                            // last pass, radix R2, Ns = N / R2
+        constexpr int Ns = P::NB2;
+        float2 v[R2];
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v[r] = row[j + r * P::NB2];
+        float2 w = tw[j];
+        w.y *= -1.0f;
+        float2 wp[R2];
+        twiddle_powers<R2>(w, wp);
+#pragma unroll
+        for (int r = 1; r < R2; ++r) v[r] = cmul(v[r], wp[r]);
+        dft<R2>(v, 1.0f);
+#pragma unroll
+        for (int q = 0; q < R2; ++q) out(f, j + q * Ns, v[q]);
+    }
+}
+
+// Column items of a fixed plan: T band columns of one plane pair per
+// workgroup (the runtime path's fields_cols_item, one butterfly per thread).
+template <int R0, int R1, int R2, int T>
+__global__ void __launch_bounds__((FixedPlan<R0, R1, R2, T>::NT))
+    fields_cols_fixed(FieldPlan fp, float2* __restrict__ V, float2* __restrict__ twx_out, int nchunks) {
+    using P = FixedPlan<R0, R1, R2, T>;
+    constexpr int N = P::N;
+    extern __shared__ float2 smem[];
+    float2* buf = smem;
+    float2* tw = smem + T * P::LD;
+    float* filt = reinterpret_cast<float*>(tw + N);
+    const int item = blockIdx.x;
+    const int q = item / nchunks, j0 = (item - q * nchunks) * T;
+    if (item == 0) fill_twiddles(twx_out, fp.Nfx);
+    fill_twiddles(tw, N);
+    for (int i = threadIdx.x; i <= 2 * fp.kcy; i += P::NT) {
+        const int k = i <= fp.kcy ? i : N - (i - fp.kcy);
+        filt[k] = gauss_filter(k, N, fp.corr_len);
+    }
+    __syncthreads();
+    int f1, j1;
+    const bool first = fixed_first<R0, R1, R2, T>(f1, j1);
+    const int jme = j0 + f1;
+    const bool col_ok = jme < fp.Mx;
+    const int kx = band_to_bin(jme, fp.kcx, fp.Nfx, fp.Mx);
+    const float hx = col_ok ? gauss_filter(kx, fp.Nfx, fp.corr_len) * fp.norm : 0.0f;
+    auto noise = [&](int, int ky) -> float2 {
+        const int kyw = ky < (N + 1) / 2 ? ky : N - ky;
+        if (!col_ok || kyw > fp.kcy) return make_float2(0.f, 0.f);
+        const float h = hx * filt[ky];
+        const float2 z = bin_noise(kx, ky, q, fp.k0, fp.k1);
+        return make_float2(h * z.x, h * z.y);
+    };
+    const int H = fp.H, Mx = fp.Mx;
+    float2* Vq = V + (size_t)q * Mx * H;
+    auto out = [&](int c, int y, float2 v) {
+        const int j = j0 + c;
+        if (y < H && j < Mx) Vq[(size_t)j * H + y] = v;
+    };
+    float2 a = make_float2(0.f, 0.f), b = a;
+    if (first) {
+        a = noise(f1, j1);
+        b = noise(f1, j1 + N - P::NB0);
+    }
+    fixed_ifft<R0, R1, R2, T>(buf, tw, a, b, out);
+}
+
+// Row items of a fixed plan: T output rows of one plane pair per workgroup,
+// in the XCD order of fields_rows_kernel.
+template <int R0, int R1, int R2, int T>
+__global__ void __launch_bounds__((FixedPlan<R0, R1, R2, T>::NT))
+    fields_rows_fixed(FieldPlan fp, const float2* __restrict__ V, float* __restrict__ F,
+                      const float2* __restrict__ twx, int nchunks) {
+    using P = FixedPlan<R0, R1, R2, T>;
+    constexpr int N = P::N;
+    extern __shared__ float2 smem[];
+    float2* buf = smem;
+    float2* tw = smem + T * P::LD;
+    const int item = xcd_row_item(blockIdx.x);
+    if (item >= nchunks * fp.npairs) return;
+    const int q = item / nchunks, y0 = (item - q * nchunks) * T;
+    const int H = fp.H, W = fp.W, Mx = fp.Mx, kcx = fp.kcx;
+    const float2* Vq = V + (size_t)q * Mx * H;
+    auto band = [&](int r, int b) -> float2 {
+        const int y = y0 + r;
+        const int j = bin_to_band(b, kcx, N, Mx);
+        return (y < H && j >= 0) ? Vq[(size_t)j * H + y] : make_float2(0.f, 0.f);
+    };
+    int f1, j1;
+    float2 a = make_float2(0.f, 0.f), b = a;
+    if (fixed_first<R0, R1, R2, T>(f1, j1)) {     // inputs in flight during the table copy
+        a = band(f1, j1);
+        b = band(f1, j1 + N - P::NB0);
+    }
+    for (int k = threadIdx.x; k < N; k += P::NT) tw[k] = twx[k];
+    __syncthreads();
+    const int p0 = 2 * q, p1 = 2 * q + 1;
+    const float s0 = fp.sigma[p0];
+    const bool has1 = p1 < fp.nplanes;
+    const float s1 = has1 ? fp.sigma[p1] : 0.0f;
+    float* F0 = F + (size_t)p0 * H * W;
+    float* F1 = F + (size_t)p1 * H * W;
+    auto out = [&](int r, int x, float2 v) {
+        const int y = y0 + r;
+        if (y >= H || x >= W) return;
+        F0[(size_t)y * W + x] = s0 * v.x;
+        if (has1) F1[(size_t)y * W + x] = s1 * v.y;
+    };
+    fixed_ifft<R0, R1, R2, T>(buf, tw, a, b, out);
+}
+
 __global__ void debug_noise_kernel(int Nfy, int Nfx, int pair, uint32_t k0, uint32_t k1, uint32_t* raw,
                                    float* normals) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -632,6 +823,14 @@ int factor_radices(int n, int* rad) {
     return n == 1 ? k : 0;
 }
 
+// Whether a transform runs on the fixed 576-point plan (9 x 8 x 8, the grid
+// of 512-pixel sides at the default correlation length): its radices are
+// those and its band lies inside the sparse first pass.
+static bool fixed_576(int N, const int* rad, int nrad, int band_lo, int band_hi) {
+    return N == 576 && nrad == 3 && rad[0] == 9 && rad[1] == 8 && rad[2] == 8 && band_lo < 64 && band_hi <= 64;
+}
+constexpr int kFixedColsT = 4, kFixedRowsT = 4;   // transforms per workgroup
+
 hipError_t launch_fields(const FieldPlan& fp, float* V, float* F, hipStream_t s) {
     const size_t kMaxLds = 160 * 1024;
     const int lc = fields_pick_lg(fp.Nfy, kColsLdsBudget, true);
@@ -661,12 +860,26 @@ hipError_t launch_fields(const FieldPlan& fp, float* V, float* F, hipStream_t s)
         res_r_lds = br;
     }
     const int nc = (fp.Mx + (1 << lc) - 1) >> lc, nr = (fp.H + (1 << lr) - 1) >> lr;
-    hipLaunchKernelGGL(fields_cols_kernel, dim3(std::min(nc * fp.npairs, res_c)), dim3(kThreads), bc, s, fp, V2, lc,
-                       twx, nc);
+    if (fixed_576(fp.Nfy, fp.rad_y, fp.nrad_y, fp.kcy, fp.kcy)) {
+        using P = FixedPlan<9, 8, 8, kFixedColsT>;
+        const int chunks = (fp.Mx + kFixedColsT - 1) / kFixedColsT;
+        hipLaunchKernelGGL((fields_cols_fixed<9, 8, 8, kFixedColsT>), dim3(chunks * fp.npairs), dim3(P::NT),
+                           P::lds_bytes + (size_t)P::N * 4, s, fp, V2, twx, chunks);
+    } else {
+        hipLaunchKernelGGL(fields_cols_kernel, dim3(std::min(nc * fp.npairs, res_c)), dim3(kThreads), bc, s, fp, V2,
+                           lc, twx, nc);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fields_rows_kernel, dim3(std::min(nr * fp.npairs, res_r)), dim3(kThreads), br, s, fp,
-                       (const float2*)V2, F, lr, (const float2*)twx, nr);
+    if (fixed_576(fp.Nfx, fp.rad_x, fp.nrad_x, fp.kcx, fp.Mx - 1 - fp.kcx)) {
+        using P = FixedPlan<9, 8, 8, kFixedRowsT>;
+        const int chunks = (fp.H + kFixedRowsT - 1) / kFixedRowsT;
+        hipLaunchKernelGGL((fields_rows_fixed<9, 8, 8, kFixedRowsT>), dim3((chunks * fp.npairs + 31) & ~31),
+                           dim3(P::NT), P::lds_bytes, s, fp, (const float2*)V2, F, (const float2*)twx, chunks);
+    } else {
+        hipLaunchKernelGGL(fields_rows_kernel, dim3(std::min(nr * fp.npairs, res_r)), dim3(kThreads), br, s, fp,
+                           (const float2*)V2, F, lr, (const float2*)twx, nr);
+    }
     return hipGetLastError();
 }
 

@@ -86,6 +86,23 @@ def test_batch_equals_solo(p2s, small_sim, prec):
         assert np.array_equal(got, solo), (k, SMALL_FRAMES[k], np.abs(got - solo).max())
 
 
+def test_batch_512_sides_equal_solo(p2s, small_sim):
+    """A frame with a 512-pixel side runs its field transforms on the fixed
+    576-point plan when alone and on the runtime-sized passes inside a batch;
+    both do the same arithmetic, so the frames agree bit for bit."""
+    sim = small_sim[0]
+    shapes = [(1, 512, 512), (3, 512, 72), (1, 40, 512)]
+    imgs = [S.blob_image(H, W, C, 950 + i, noise_std=0.01) for i, (C, H, W) in enumerate(shapes)]
+    d, seeds = [2.0, 1.0, 3.5], [31, 32, 33]
+    dimgs = [dev(im) for im in imgs]
+    for prec in ("fp32", "bf16"):
+        outs = sim.batch(dimgs, d, seeds, prec)
+        for k, im in enumerate(dimgs):
+            solo = host(sim(im, d[k], seeds[k], prec))
+            got = host(outs[k])
+            assert np.array_equal(got, solo), (shapes[k], prec, np.abs(got - solo).max())
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_batch_frame_vs_oracle(p2s, small_sim, prec):
     sim, B, Ws, bs = small_sim
