@@ -573,6 +573,23 @@ __global__ void __launch_bounds__(kThreads) fields_rows_batch(const FrameDesc* _
 // LDS row of its transform; the middle pass reads its R1 inputs, waits for
 // the whole workgroup, and overwrites them in place; the last pass reads
 // and hands each output to out(f, index, value).
+// Entry m of the table fill_twiddles writes for an N-point transform, bit
+// for bit (the same FP64 evaluation and the same exact quarter moves).
+__device__ __forceinline__ float2 twiddle_entry(int m, int N) {
+    const bool quarter = (N & 3) == 0;
+    const int n = quarter ? N >> 2 : N;
+    const int quad = m / n, q = m - quad * n;
+    double sn, cs;
+    sincospi(-2.0 * (double)q / (double)N, &sn, &cs);
+    const float fc = (float)cs, fs = (float)sn;
+    switch (quad) {
+        case 0: return make_float2(fc, fs);
+        case 1: return make_float2(fs, -fc);
+        case 2: return make_float2(-fc, -fs);
+        default: return make_float2(-fs, fc);
+    }
+}
+
 template <int R0, int R1, int R2, int T>
 struct FixedPlan {
     static constexpr int N = R0 * R1 * R2;
@@ -580,7 +597,15 @@ struct FixedPlan {
     static constexpr int TPF = NB0 > NB1 ? (NB0 > NB2 ? NB0 : NB2) : (NB1 > NB2 ? NB1 : NB2);
     static constexpr int NT = T * TPF;
     static constexpr int LD = N | 1;
-    static constexpr size_t lds_bytes = (size_t)(T * LD + N) * 8;
+    // the twiddles the passes use: entries 0 .. NB2-1 of the table (the last
+    // pass, and the middle pass's k R2 < NB2), then k NB0 for k < R0 (the
+    // first pass) at NB2 + k
+    static constexpr int NTW = NB2 + R0;
+    static_assert((R0 - 1) * R2 < NB2, "middle-pass twiddles inside the first NB2 entries");
+    static constexpr size_t lds_bytes = (size_t)(T * LD + NTW) * 8;
+    __device__ static void fill_table(float2* ct) {
+        for (int i = threadIdx.x; i < NTW; i += NT) ct[i] = twiddle_entry(i < NB2 ? i : (i - NB2) * NB0, N);
+    }
 };
 
 // The first pass's butterfly of this thread: transform t % T, butterfly
@@ -596,8 +621,11 @@ __device__ __forceinline__ bool fixed_first(int& f, int& j) {
 }
 
 // The transforms of one workgroup; a = x[j], b = x[j + N - N/R0] are the
-// inputs of this thread's first-pass butterfly (fixed_first), the twiddle
-// table tw is in place and a barrier has passed since it was written.
+// inputs of this thread's first-pass butterfly (fixed_first), the compact
+// twiddle table tw (FixedPlan::fill_table) is in place and a barrier has
+// passed since it was written.  out(f, j, v) takes the last-pass butterfly j of transform f: outputs
+// j + q N/R2 in v[q] (q < R2), so that the caller forms one address per
+// butterfly and stores at constant offsets from it.
 template <int R0, int R1, int R2, int T, class Out>
 __device__ __forceinline__ void fixed_ifft(float2* __restrict__ buf, const float2* __restrict__ tw, float2 a,
                                            float2 b, Out&& out) {
@@ -608,7 +636,7 @@ __device__ __forceinline__ void fixed_ifft(float2* __restrict__ buf, const float
         const int f = f1, j = j1;
         float2 w[R0];
 #pragma unroll
-        for (int k = 0; k < R0; ++k) w[k] = tw[k * P::NB0];
+        for (int k = 0; k < R0; ++k) w[k] = tw[P::NB2 + k];
         float2* row = buf + f * LD + j * R0;
 #pragma unroll
         for (int k = 0; k < R0; ++k)
@@ -653,8 +681,7 @@ __device__ __forceinline__ void fixed_ifft(float2* __restrict__ buf, const float
 #pragma unroll
         for (int r = 1; r < R2; ++r) v[r] = cmul(v[r], wp[r]);
         dft<R2>(v, 1.0f);
-#pragma unroll
-        for (int q = 0; q < R2; ++q) out(f, j + q * Ns, v[q]);
+        out(f, j, v);
     }
 }
 
@@ -668,14 +695,14 @@ __global__ void __launch_bounds__((FixedPlan<R0, R1, R2, T>::NT))
     extern __shared__ float2 smem[];
     float2* buf = smem;
     float2* tw = smem + T * P::LD;
-    float* filt = reinterpret_cast<float*>(tw + N);
+    float* filt = reinterpret_cast<float*>(tw + P::NTW);   // band rows: |ky| at |ky|, -|ky| at kcy + |ky|
     const int item = blockIdx.x;
     const int q = item / nchunks, j0 = (item - q * nchunks) * T;
     if (item == 0) fill_twiddles(twx_out, fp.Nfx);
-    fill_twiddles(tw, N);
+    P::fill_table(tw);
     for (int i = threadIdx.x; i <= 2 * fp.kcy; i += P::NT) {
         const int k = i <= fp.kcy ? i : N - (i - fp.kcy);
-        filt[k] = gauss_filter(k, N, fp.corr_len);
+        filt[i] = gauss_filter(k, N, fp.corr_len);
     }
     __syncthreads();
     int f1, j1;
@@ -687,15 +714,18 @@ __global__ void __launch_bounds__((FixedPlan<R0, R1, R2, T>::NT))
     auto noise = [&](int, int ky) -> float2 {
         const int kyw = ky < (N + 1) / 2 ? ky : N - ky;
         if (!col_ok || kyw > fp.kcy) return make_float2(0.f, 0.f);
-        const float h = hx * filt[ky];
+        const float h = hx * filt[ky < (N + 1) / 2 ? kyw : fp.kcy + kyw];
         const float2 z = bin_noise(kx, ky, q, fp.k0, fp.k1);
         return make_float2(h * z.x, h * z.y);
     };
     const int H = fp.H, Mx = fp.Mx;
     float2* Vq = V + (size_t)q * Mx * H;
-    auto out = [&](int c, int y, float2 v) {
-        const int j = j0 + c;
-        if (y < H && j < Mx) Vq[(size_t)j * H + y] = v;
+    auto out = [&](int c, int y, const float2 (&v)[R2]) {
+        if (j0 + c >= Mx) return;
+        float2* col = Vq + (size_t)(j0 + c) * H + y;
+#pragma unroll
+        for (int q = 0; q < R2; ++q)
+            if (y + q * P::NB2 < H) col[q * P::NB2] = v[q];
     };
     float2 a = make_float2(0.f, 0.f), b = a;
     if (first) {
@@ -709,8 +739,7 @@ __global__ void __launch_bounds__((FixedPlan<R0, R1, R2, T>::NT))
 // in the XCD order of fields_rows_kernel.
 template <int R0, int R1, int R2, int T>
 __global__ void __launch_bounds__((FixedPlan<R0, R1, R2, T>::NT))
-    fields_rows_fixed(FieldPlan fp, const float2* __restrict__ V, float* __restrict__ F,
-                      const float2* __restrict__ twx, int nchunks) {
+    fields_rows_fixed(FieldPlan fp, const float2* __restrict__ V, float* __restrict__ F, int nchunks) {
     using P = FixedPlan<R0, R1, R2, T>;
     constexpr int N = P::N;
     extern __shared__ float2 smem[];
@@ -732,7 +761,7 @@ __global__ void __launch_bounds__((FixedPlan<R0, R1, R2, T>::NT))
         a = band(f1, j1);
         b = band(f1, j1 + N - P::NB0);
     }
-    for (int k = threadIdx.x; k < N; k += P::NT) tw[k] = twx[k];
+    P::fill_table(tw);
     __syncthreads();
     const int p0 = 2 * q, p1 = 2 * q + 1;
     const float s0 = fp.sigma[p0];
@@ -740,11 +769,17 @@ __global__ void __launch_bounds__((FixedPlan<R0, R1, R2, T>::NT))
     const float s1 = has1 ? fp.sigma[p1] : 0.0f;
     float* F0 = F + (size_t)p0 * H * W;
     float* F1 = F + (size_t)p1 * H * W;
-    auto out = [&](int r, int x, float2 v) {
+    auto out = [&](int r, int x, const float2 (&v)[R2]) {
         const int y = y0 + r;
-        if (y >= H || x >= W) return;
-        F0[(size_t)y * W + x] = s0 * v.x;
-        if (has1) F1[(size_t)y * W + x] = s1 * v.y;
+        if (y >= H) return;
+        float* o0 = F0 + (size_t)y * W + x;
+        float* o1 = F1 + (size_t)y * W + x;
+#pragma unroll
+        for (int q = 0; q < R2; ++q) {
+            if (x + q * P::NB2 >= W) continue;
+            o0[q * P::NB2] = s0 * v[q].x;
+            if (has1) o1[q * P::NB2] = s1 * v[q].y;
+        }
     };
     fixed_ifft<R0, R1, R2, T>(buf, tw, a, b, out);
 }
@@ -829,6 +864,7 @@ int factor_radices(int n, int* rad) {
 static bool fixed_576(int N, const int* rad, int nrad, int band_lo, int band_hi) {
     return N == 576 && nrad == 3 && rad[0] == 9 && rad[1] == 8 && rad[2] == 8 && band_lo < 64 && band_hi <= 64;
 }
+constexpr size_t kFixedBandRows = 128;             // filter factors of the band rows (2 kcy + 1 <= 127)
 constexpr int kFixedColsT = 4, kFixedRowsT = 4;   // transforms per workgroup
 
 hipError_t launch_fields(const FieldPlan& fp, float* V, float* F, hipStream_t s) {
@@ -864,7 +900,7 @@ hipError_t launch_fields(const FieldPlan& fp, float* V, float* F, hipStream_t s)
         using P = FixedPlan<9, 8, 8, kFixedColsT>;
         const int chunks = (fp.Mx + kFixedColsT - 1) / kFixedColsT;
         hipLaunchKernelGGL((fields_cols_fixed<9, 8, 8, kFixedColsT>), dim3(chunks * fp.npairs), dim3(P::NT),
-                           P::lds_bytes + (size_t)P::N * 4, s, fp, V2, twx, chunks);
+                           P::lds_bytes + kFixedBandRows * 4, s, fp, V2, twx, chunks);
     } else {
         hipLaunchKernelGGL(fields_cols_kernel, dim3(std::min(nc * fp.npairs, res_c)), dim3(kThreads), bc, s, fp, V2,
                            lc, twx, nc);
@@ -875,7 +911,7 @@ hipError_t launch_fields(const FieldPlan& fp, float* V, float* F, hipStream_t s)
         using P = FixedPlan<9, 8, 8, kFixedRowsT>;
         const int chunks = (fp.H + kFixedRowsT - 1) / kFixedRowsT;
         hipLaunchKernelGGL((fields_rows_fixed<9, 8, 8, kFixedRowsT>), dim3((chunks * fp.npairs + 31) & ~31),
-                           dim3(P::NT), P::lds_bytes, s, fp, (const float2*)V2, F, (const float2*)twx, chunks);
+                           dim3(P::NT), P::lds_bytes, s, fp, (const float2*)V2, F, chunks);
     } else {
         hipLaunchKernelGGL(fields_rows_kernel, dim3(std::min(nr * fp.npairs, res_r)), dim3(kThreads), br, s, fp,
                            (const float2*)V2, F, lr, (const float2*)twx, nr);
