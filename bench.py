@@ -264,23 +264,28 @@ def pipeline_times(torch, p2s, sim, img, fr, NZ, H, W, prec, frames, stream, see
     three stage calls (fields, network and blur in one kernel, warp), with no
     synchronisation, `frames` frames
       (a) with HIP events on the launch stream around every network-and-blur
-          launch (each event adds a little time of its own), and
-      (b) back to back with and without that kernel, events only around the
-          whole loop: the difference per frame is the kernel's share.
-    Returns (events mean us, difference us, frame us)."""
+          launch (each event adds a little time of its own),
+      (b) back to back with the kernel launched twice per frame and once,
+          events only around the whole loop: the difference per frame is one
+          launch's duration plus the short gap between two launches, and
+      (c) with the kernel once and not at all: the difference is the frame
+          time the kernel adds, less than its duration, because the launch
+          gaps of the short field and warp kernels hide behind a long kernel
+          and are exposed without it.
+    Returns (events mean us, (b) us, frame us, (c) us)."""
     F = torch.empty((NZ, H, W), dtype=torch.float32, device="cuda")
     fws = torch.empty(p2s.fields_workspace_bytes(H, W, NZ), dtype=torch.uint8, device="cuda")
     bl = torch.empty_like(img)
     out = torch.empty_like(img)
 
-    def loop(with_kernel, ev=None):
+    def loop(launches, ev=None):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for i in range(frames):
             p2s.make_fields(H, W, fr.d_over_r0, NZ, seed0 + 10 + i, F, fws)
             if ev is not None:
                 ev[i][0].record(stream)
-            if with_kernel:
+            for _ in range(launches):
                 p2s.mlp_blur(sim.net, F, NZ, img, sim.basis, prec, bl)
             if ev is not None:
                 ev[i][1].record(stream)
@@ -295,23 +300,25 @@ def pipeline_times(torch, p2s, sim, img, fr, NZ, H, W, prec, frames, stream, see
         p2s.warp(bl, F, out)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(frames)]
-    loop(True, ev)
+    loop(1, ev)
     per = float(np.mean([a.elapsed_time(b) * 1e3 for a, b in ev]))
-    full = loop(True)
-    without = loop(False)
-    full = min(full, loop(True))
-    return per, full - without, full
+    full = loop(1)
+    twice = loop(2)
+    without = loop(0)
+    full = min(full, loop(1))
+    return per, twice - full, full, full - without
 
 
 def pipeline_mode(args, torch, p2s, sim, img, fr, NZ, H, W, K, P, C, dims):
     """The dominant kernel timed inside the frame pipeline (pipeline_times),
     args.steps frames: the command whose kernel trace is committed beside the
     benchmark's roofline figure."""
-    ev_us, us, frame_us = pipeline_times(torch, p2s, sim, img, fr, NZ, H, W, args.precision, args.steps,
-                                         torch.cuda.current_stream())
+    ev_us, us, frame_us, share_us = pipeline_times(torch, p2s, sim, img, fr, NZ, H, W, args.precision, args.steps,
+                                                   torch.cuda.current_stream())
     fl = blur_flops(C, H, W, K, P) + mlp_flops(H, W, dims)
     print(json.dumps({"mode": "pipeline", "precision": args.precision, "frames": args.steps,
                       "mlp_blur_avg_us": us, "mlp_blur_events_us": ev_us, "frame_us": frame_us,
+                      "frame_share_us": share_us,
                       "TFLOPs": fl / us / 1e6, "algorithmic_flops_per_launch": fl}), flush=True)
 
 
@@ -749,13 +756,15 @@ def main():
         res[prec]["stages_us"] = stages
         if fused:
             # the dominant kernel's average duration inside the frame pipeline
-            ev_us, us, frame_us = pipeline_times(torch, p2s, sim, img, fr, NZ, H, W, prec, args.pipeline_frames,
-                                                 stream)
+            ev_us, us, frame_us, share_us = pipeline_times(torch, p2s, sim, img, fr, NZ, H, W, prec,
+                                                           args.pipeline_frames, stream)
             res[prec]["mlp_blur_loop_us"] = us
             res[prec]["mlp_blur_events_us"] = ev_us
             res[prec]["pipeline_frame_us"] = frame_us
+            res[prec]["mlp_blur_frame_share_us"] = share_us
             log(f"[bench] {prec} network+blur kernel inside the frame pipeline: {us:.1f} us "
-                f"(events around each launch: {ev_us:.1f} us; {frame_us:.1f} us per frame)")
+                f"(events around each launch: {ev_us:.1f} us; it adds {share_us:.1f} us to a frame of "
+                f"{frame_us:.1f} us)")
         log(f"[bench] {prec} stages (us): " + ", ".join(f"{k} {v:.1f}" for k, v in res[prec]["stages_us"].items()))
         del wbuf, fws, bl
 
@@ -776,9 +785,11 @@ def main():
                 "algorithmic_flops_per_launch": flops + nflops,
                 "algorithmic_flops_split": {"blur": flops, "network": nflops},
                 "avg_launch_us": fused_s * 1e6, "src_digest": src_digest(*kernel_src),
-                "timing": f"{args.pipeline_frames} back-to-back frames (fields, network and blur, warp) with and "
-                          f"without the kernel, per-frame difference, as bench.py --mode pipeline",
+                "timing": f"{args.pipeline_frames} back-to-back frames (fields, network and blur, warp) with the "
+                          f"kernel launched twice and once per frame, per-frame difference, as bench.py --mode "
+                          f"pipeline",
                 "events_around_each_launch_us": res["bf16"]["mlp_blur_events_us"],
+                "frame_share_us": res["bf16"]["mlp_blur_frame_share_us"],
                 "blur_only": {"kernel": "blur_bf16_kernel<33,7,8> (w read from memory)", "avg_launch_us": blur_s * 1e6,
                               "achieved": flops / blur_s / 1e12, "frac": flops / blur_s / 1e12 / PEAK_BF16_TFLOPS}}
     fp32_blur_s = res["fp32"]["stages_us"]["blur"] * 1e-6
