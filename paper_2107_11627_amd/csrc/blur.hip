@@ -194,7 +194,7 @@ struct WFromNetwork {
 // other channels without), and both instances share these buffers.
 template <class T, int N, int TAG>
 __device__ __forceinline__ T* lds_buffer() {
-    __shared__ T buf[N];
+    __shared__ __attribute__((aligned(16))) T buf[N];
     return buf;
 }
 
@@ -246,7 +246,10 @@ __device__ __forceinline__ void stage_window(float* __restrict__ dst, int ld, co
 // Rows of the staged fp32 window of a low-precision tile (P taps, 2 NBLK
 // output rows); the stage has a pitch of 64 floats (kTX + 2 R <= 64), one
 // row per wave-wide copy instruction.
-constexpr int kStagePitch = 64;
+// Staged rows start 68 floats apart: 17 x 16 bytes, an odd number of 16-byte
+// units, so that 16-byte reads of the same columns of consecutive rows fall
+// on different LDS banks (the chunk packing reads rows that way).
+constexpr int kStagePitch = 68;
 template <int P, int NBLK>
 struct TileGeom {
     static constexpr int R = (P - 1) / 2;
@@ -260,6 +263,98 @@ struct TileGeom {
 template <int P, int NBLK>
 __device__ __forceinline__ float* stage_lds() {
     return lds_buffer<float, TileGeom<P, NBLK>::SH * kStagePitch, 2>();
+}
+
+// Entries of the row- and column-chunk layouts, eight at a time: from a run of
+// 16 consecutive staged values v (a row run or a column run) entry k holds
+// values k .. k+7, i.e. bytes k .. k+7 of the run's E4M3 codes or 16-bit
+// lanes k .. k+7 of its bf16 codes; v[15] falls in no window.  Every value
+// is converted once (the conversions are elementwise, so an entry is the
+// same as converting its 8 values directly) and the windows are byte
+// alignments of neighbouring code words.
+__device__ __forceinline__ void bf16_windows8(const float (&v)[16], uint4 (&e)[8]) {
+    const floatx8 a = {v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+    const floatx8 b = {v[8], v[9], v[10], v[11], v[12], v[13], v[14], v[15]};
+    const uint4 wa = __builtin_bit_cast(uint4, to_bf16x8(a)), wb = __builtin_bit_cast(uint4, to_bf16x8(b));
+    const uint32_t w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int i = k >> 1;
+        if (k & 1)
+            e[k] = make_uint4(__builtin_amdgcn_alignbyte(w[i + 1], w[i], 2), __builtin_amdgcn_alignbyte(w[i + 2], w[i + 1], 2),
+                              __builtin_amdgcn_alignbyte(w[i + 3], w[i + 2], 2), __builtin_amdgcn_alignbyte(w[i + 4], w[i + 3], 2));
+        else
+            e[k] = make_uint4(w[i], w[i + 1], w[i + 2], w[i + 3]);
+    }
+}
+
+// E4M3 codes after clamping to +-448 (one med3), rounded to nearest even.
+__device__ __forceinline__ void e4m3_windows8(const float (&v)[16], uint2 (&e)[8]) {
+    uint32_t d[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = __builtin_amdgcn_fmed3f(v[4 * i + j], -448.0f, 448.0f);
+        d[i] = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(c[0], c[1], 0, false);
+        d[i] = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(c[2], c[3], (int)d[i], true);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int m = k >> 2, sh = k & 3;
+        e[k] = sh ? make_uint2(__builtin_amdgcn_alignbyte(d[m + 1], d[m], sh), __builtin_amdgcn_alignbyte(d[m + 2], d[m + 1], sh))
+                  : make_uint2(d[m], d[m + 1]);
+    }
+}
+
+// Both chunk layouts of a staged window.  Row units: entries p0 .. p0+7 of
+// one layout row r (row r of the stage, 4 reads of 16 bytes), taken
+// row-fastest, so that with an odd entry pitch (and the odd 16-byte pitch
+// of the stage) the lanes' reads and writes spread over the LDS banks.
+// Column units: entries r0 .. r0+7 of one column (15 values down staged
+// column q + 2R), column-fastest.  ALL: fully unrolled (the fused kernels
+// have the registers free here).
+template <int P, int NBLK, bool ALL, class E, class Conv>
+__device__ __forceinline__ void pack_chunks(const float* __restrict__ stage, E* __restrict__ rowpk, int rpitch,
+                                            E* __restrict__ colpk, int cpitch, Conv&& conv) {
+    using G = TileGeom<P, NBLK>;
+    constexpr int R = G::R, PH = G::PH, QH = G::QH, SH = G::SH;
+    constexpr int RG = (kTX + 8 * (P / 8 - 1)) / 8;   // 8-entry groups per layout row
+    constexpr int CG = (QH + 7) / 8;
+    constexpr int UR = PH * RG, U = UR + CG * kTX;
+    auto unit = [&](int u) {
+        float v[16];
+        E e[8];
+        if (u < UR) {
+            const int r = u % PH, p0 = (u / PH) * 8;
+            const float4* src = reinterpret_cast<const float4*>(stage + r * kStagePitch + p0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float4 x = src[i];
+                v[4 * i] = x.x;
+                v[4 * i + 1] = x.y;
+                v[4 * i + 2] = x.z;
+                v[4 * i + 3] = x.w;
+            }
+            conv(v, e);
+            E* dst = rowpk + r * rpitch + p0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) dst[k] = e[k];
+        } else {
+            const int uc = u - UR;
+            const int q = uc % kTX, r0 = (uc / kTX) * 8;
+            const float* src = stage + r0 * kStagePitch + q + 2 * R;
+#pragma unroll
+            for (int i = 0; i < 15; ++i) v[i] = (QH % 8 == 0 || r0 + i < SH) ? src[i * kStagePitch] : 0.0f;
+            v[15] = 0.0f;
+            conv(v, e);
+            E* dst = colpk + r0 * cpitch + q;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (QH % 8 == 0 || r0 + k < QH) dst[k * cpitch] = e[k];
+        }
+    };
+    for_block_items<U, ALL>(unit);
 }
 
 // The image window a tile item stages: rows y_lo.., columns x_lo.. of
@@ -508,17 +603,6 @@ __device__ __forceinline__ void blur_bf16_tile(const float* __restrict__ img, in
 // the E8M0 scale 2^-e_k of that basis function, so the accumulators hold the
 // unscaled convolutions and the epilogue is the one of the other precisions.
 // The image is rounded to E4M3 (ties to even) after clamping to +-448.
-__device__ __forceinline__ uint2 pack_e4m3x8(const float* s, int stride) {
-    float v[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = __builtin_amdgcn_fmed3f(s[e * stride], -448.0f, 448.0f);   // clamp, one op
-    uint32_t lo = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false) & 0xFFFFu;
-    lo |= ((uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], 0, false) & 0xFFFFu) << 16;
-    uint32_t hi = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], 0, false) & 0xFFFFu;
-    hi |= ((uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], 0, false) & 0xFFFFu) << 16;
-    return make_uint2(lo, hi);
-}
-
 template <int P, int NMB, int NBLK, bool DMA = false, class Epi>
 __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int H, int W,
                                               const uint4* __restrict__ bp, const int* __restrict__ scale,
@@ -529,7 +613,7 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
     constexpr int NCOL = (P + 7) / 8;
     constexpr int T128 = (NROW + NCOL + 15) / 16;
     constexpr int TY = NBLK * 2;
-    constexpr int PITCH = kTX + 8 * (A8 - 1);
+    constexpr int PITCH = (kTX + 8 * (A8 - 1)) | 1;   // odd: see pack_chunks
     constexpr int PH = TY + 2 * R;
     constexpr int QH = TY + 8 * (NCOL - 1);
     constexpr int NR = PH > QH ? PH : QH;
@@ -558,14 +642,8 @@ __device__ __forceinline__ void blur_fp8_tile(const float* __restrict__ img, int
         stage_window<14>(stage8, SW, ic, H, W, y0 - R, x0 - R, SH, kTX + 2 * R);
         __syncthreads();
     }
-    for_block_items<PH * PITCH, DMA>([&](int idx) {
-        const int r = idx / PITCH, p = idx - r * PITCH;
-        rowpk8[idx] = pack_e4m3x8(stage8 + r * SW + p, 1);
-    });
-    for_block_items<QH * kTX, DMA>([&](int idx) {
-        const int r = idx / kTX, q = idx - r * kTX;
-        colpk8[r * PITCH + q] = pack_e4m3x8(stage8 + r * SW + q + 2 * R, SW);
-    });
+    pack_chunks<P, NBLK, DMA>(stage8, rowpk8, PITCH, colpk8, PITCH,
+                              [](const float (&v)[16], uint2 (&e)[8]) { e4m3_windows8(v, e); });
     __syncthreads();
     if constexpr (DMA) {
         epi.settle();
