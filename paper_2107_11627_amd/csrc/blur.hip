@@ -265,30 +265,13 @@ __device__ __forceinline__ float* stage_lds() {
     return lds_buffer<float, TileGeom<P, NBLK>::SH * kStagePitch, 2>();
 }
 
-// Entries of the row- and column-chunk layouts, eight at a time: from a run of
-// 16 consecutive staged values v (a row run or a column run) entry k holds
-// values k .. k+7, i.e. bytes k .. k+7 of the run's E4M3 codes or 16-bit
-// lanes k .. k+7 of its bf16 codes; v[15] falls in no window.  Every value
-// is converted once (the conversions are elementwise, so an entry is the
-// same as converting its 8 values directly) and the windows are byte
-// alignments of neighbouring code words.
-__device__ __forceinline__ void bf16_windows8(const float (&v)[16], uint4 (&e)[8]) {
-    const floatx8 a = {v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
-    const floatx8 b = {v[8], v[9], v[10], v[11], v[12], v[13], v[14], v[15]};
-    const uint4 wa = __builtin_bit_cast(uint4, to_bf16x8(a)), wb = __builtin_bit_cast(uint4, to_bf16x8(b));
-    const uint32_t w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int i = k >> 1;
-        if (k & 1)
-            e[k] = make_uint4(__builtin_amdgcn_alignbyte(w[i + 1], w[i], 2), __builtin_amdgcn_alignbyte(w[i + 2], w[i + 1], 2),
-                              __builtin_amdgcn_alignbyte(w[i + 3], w[i + 2], 2), __builtin_amdgcn_alignbyte(w[i + 4], w[i + 3], 2));
-        else
-            e[k] = make_uint4(w[i], w[i + 1], w[i + 2], w[i + 3]);
-    }
-}
-
-// E4M3 codes after clamping to +-448 (one med3), rounded to nearest even.
+// Entries of the FP8 row- and column-chunk layouts, eight at a time: from a
+// run of 16 consecutive staged values v (a row run or a column run) entry k
+// holds values k .. k+7, i.e. bytes k .. k+7 of the run's E4M3 codes; v[15]
+// falls in no window.  Every value is converted once (the conversion is
+// elementwise, so an entry equals converting its 8 values directly) and the
+// windows are byte alignments of neighbouring code words.  The codes are
+// those of the values clamped to +-448 (one med3), rounded to nearest even.
 __device__ __forceinline__ void e4m3_windows8(const float (&v)[16], uint2 (&e)[8]) {
     uint32_t d[4];
 #pragma unroll
@@ -307,7 +290,7 @@ __device__ __forceinline__ void e4m3_windows8(const float (&v)[16], uint2 (&e)[8
     }
 }
 
-// Both chunk layouts of a staged window.  Row units: entries p0 .. p0+7 of
+// Both FP8 chunk layouts of a staged window.  Row units: entries p0 .. p0+7 of
 // one layout row r (row r of the stage, 4 reads of 16 bytes), taken
 // row-fastest, so that with an odd entry pitch (and the odd 16-byte pitch
 // of the stage) the lanes' reads and writes spread over the LDS banks.
