@@ -16,8 +16,10 @@
 //            elsewhere -> inverse FFT along y -> V[q][y][j] for y < H
 //   rows:    for each output row y: V scattered into the band bins -> inverse
 //            FFT along x -> planes 2q, 2q+1 for x < W
-// FFTs: Stockham auto-sort in LDS, radix 4/2/3/5 passes, FP64-evaluated
-// twiddle table, thread -> (transform, butterfly) mapping by shifts.
+// FFTs: Stockham auto-sort in LDS, radix 9/8/4/2/3/5 passes, FP64-evaluated
+// twiddle table, thread -> (transform, butterfly) mapping by shifts; the
+// 576-point grid of 512-pixel sides runs on a fixed 9 x 8 x 8 plan with one
+// butterfly per thread and pass (same arithmetic, same bits).
 #include <algorithm>
 
 #include "internal.hpp"
