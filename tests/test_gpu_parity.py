@@ -86,7 +86,9 @@ def test_philox_bitwise_and_normals(p2s, Nfy, Nfx, pair, seed):
     (128, 128, 35, 1.5, 1, 16.0), (100, 150, 35, 4.0, 3000, 4.0),
     # 512-pixel sides: the fixed 576-point plan along x (ragged last row item),
     # along y (odd plane count), and a band too wide for it (runtime passes)
-    (37, 512, 35, 2.0, 77, 16.0), (512, 45, 5, 1.0, 8, 16.0), (64, 512, 6, 2.0, 5, 8.0)])
+    (37, 512, 35, 2.0, 77, 16.0), (512, 45, 5, 1.0, 8, 16.0), (64, 512, 6, 2.0, 5, 8.0),
+    # sides below 512 on the same 576-point grid: the last pass's guards on x < W and y < H
+    (100, 480, 7, 1.5, 21, 16.0), (480, 64, 4, 2.5, 22, 16.0)])
 def test_make_fields(p2s, H, W, nz, d, seed, ell):
     ws = torch.empty(p2s.fields_workspace_bytes(H, W, nz, ell), dtype=torch.uint8, device="cuda")
     F = torch.full((nz, H, W), float("nan"), dtype=torch.float32, device="cuda")
