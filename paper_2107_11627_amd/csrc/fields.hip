@@ -574,7 +574,8 @@ __global__ void __launch_bounds__(kThreads) fields_rows_batch(const FrameDesc* _
 // Passes: the sparse first pass (inputs x[j], x[j + N - N/R0]) writes the
 // LDS row of its transform; the middle pass reads its R1 inputs, waits for
 // the whole workgroup, and overwrites them in place; the last pass reads
-// and hands each output to out(f, index, value).
+// and hands its R2 outputs to the caller's store.
+
 // Entry m of the table fill_twiddles writes for an N-point transform, bit
 // for bit (the same FP64 evaluation and the same exact quarter moves).
 __device__ __forceinline__ float2 twiddle_entry(int m, int N) {
@@ -625,9 +626,9 @@ __device__ __forceinline__ bool fixed_first(int& f, int& j) {
 // The transforms of one workgroup; a = x[j], b = x[j + N - N/R0] are the
 // inputs of this thread's first-pass butterfly (fixed_first), the compact
 // twiddle table tw (FixedPlan::fill_table) is in place and a barrier has
-// passed since it was written.  out(f, j, v) takes the last-pass butterfly j of transform f: outputs
-// j + q N/R2 in v[q] (q < R2), so that the caller forms one address per
-// butterfly and stores at constant offsets from it.
+// passed since it was written.  out(f, j, v) takes the last-pass butterfly j
+// of transform f: outputs j + s N/R2 in v[s] (s < R2), so that the caller
+// forms one address per butterfly and stores at constant offsets from it.
 template <int R0, int R1, int R2, int T, class Out>
 __device__ __forceinline__ void fixed_ifft(float2* __restrict__ buf, const float2* __restrict__ tw, float2 a,
                                            float2 b, Out&& out) {
@@ -726,8 +727,8 @@ __global__ void __launch_bounds__((FixedPlan<R0, R1, R2, T>::NT))
         if (j0 + c >= Mx) return;
         float2* col = Vq + (size_t)(j0 + c) * H + y;
 #pragma unroll
-        for (int q = 0; q < R2; ++q)
-            if (y + q * P::NB2 < H) col[q * P::NB2] = v[q];
+        for (int s = 0; s < R2; ++s)
+            if (y + s * P::NB2 < H) col[s * P::NB2] = v[s];
     };
     float2 a = make_float2(0.f, 0.f), b = a;
     if (first) {
@@ -759,7 +760,7 @@ __global__ void __launch_bounds__((FixedPlan<R0, R1, R2, T>::NT))
     };
     int f1, j1;
     float2 a = make_float2(0.f, 0.f), b = a;
-    if (fixed_first<R0, R1, R2, T>(f1, j1)) {     // inputs in flight during the table copy
+    if (fixed_first<R0, R1, R2, T>(f1, j1)) {     // inputs in flight while the table is evaluated
         a = band(f1, j1);
         b = band(f1, j1 + N - P::NB0);
     }
@@ -777,10 +778,10 @@ __global__ void __launch_bounds__((FixedPlan<R0, R1, R2, T>::NT))
         float* o0 = F0 + (size_t)y * W + x;
         float* o1 = F1 + (size_t)y * W + x;
 #pragma unroll
-        for (int q = 0; q < R2; ++q) {
-            if (x + q * P::NB2 >= W) continue;
-            o0[q * P::NB2] = s0 * v[q].x;
-            if (has1) o1[q * P::NB2] = s1 * v[q].y;
+        for (int s = 0; s < R2; ++s) {
+            if (x + s * P::NB2 >= W) continue;
+            o0[s * P::NB2] = s0 * v[s].x;
+            if (has1) o1[s * P::NB2] = s1 * v[s].y;
         }
     };
     fixed_ifft<R0, R1, R2, T>(buf, tw, a, b, out);
