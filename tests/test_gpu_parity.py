@@ -255,6 +255,9 @@ def test_warp_zero_tilt_is_identity(p2s):
     ((33, 48, 48, 40), 40, 17, 2, 50, 70, "bf16"),
     ((33, 48, 48, 40), 40, 17, 2, 50, 70, "fp8"),
     ((33, 16, 16), 16, 9, 1, 33, 65, "fp8"),
+    # FP8 at the headline shape with three channels (the second tile instance), and P = 25
+    ((33, 100, 100, 100), 100, 33, 3, 37, 45, "fp8"),
+    ((33, 48, 48, 40), 40, 25, 1, 41, 50, "fp8"),
 ])
 def test_mlp_blur_fused_equals_staged(p2s, dims, K, P, C, H, W, prec):
     """The network evaluated inside the blur epilogue gives bit for bit what
